@@ -1,0 +1,179 @@
+"""Pins of the oracle's GEPP, LU_PRRP and CALU_PRRP (Sections 2 and 3).
+
+Checks against LAPACK (getrf through scipy), closed forms (GEPP growth on the
+Wilkinson and Foster matrices), invariants stated in the paper (|L_2j| <= tau,
+per-step growth <= 1 + tau b, CALU_PRRP per-step growth <= (1 + tau b)^(H+1),
+the Schur complement of the pivot rows) and the growth the paper prints for
+the Foster matrix (Table "tab_foster", fixture tests/golden/foster_lu_prrp.txt).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import lu, metrics
+from paper_1208_2451_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TAU_TOL = 1.0 + 2.0 ** -32
+
+
+def _lapack_perm(A):
+    lu_, piv = sla.lu_factor(A)
+    perm = np.arange(A.shape[0])
+    for j, p in enumerate(piv):
+        perm[[j, p]] = perm[[p, j]]
+    return lu_, perm
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_gepp_block_matches_lapack(seed):
+    A = np.random.default_rng(seed).standard_normal((48, 48))
+    B = A.copy()
+    ipiv, info = lu.gepp_inplace(B)
+    lu_, piv = sla.lu_factor(A)
+    assert info == 0
+    assert list(ipiv) == list(piv)
+    assert np.allclose(B, lu_, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_lu_prrp_b1_is_gepp(seed):
+    """With b = 1 the QRCP of a 1 x m row picks the largest |a| and |M| <= 1 < tau,
+    so LU_PRRP reduces to GEPP."""
+    A = np.random.default_rng(10 + seed).standard_normal((40, 40))
+    f = lu.lu_prrp(A, 1, 2.0)
+    lu_, perm = _lapack_perm(A)
+    assert list(f.perm) == list(perm)
+    assert np.allclose(f.LU, lu_, rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("n,b", [(64, 8), (100, 16), (96, 32), (50, 50), (77, 10)])
+def test_lu_prrp_factors_and_invariants(n, b):
+    A = np.random.default_rng(n * 31 + b).standard_normal((n, n))
+    f = lu.lu_prrp(A, b, 2.0)
+    assert sorted(f.perm) == list(range(n))
+    assert metrics.backward_error(A, f.LU, f.perm) <= 1e-15 * n
+    assert f.max_block_L <= 2.0 * TAU_TOL
+    assert f.step_growth_ok
+    assert f.g_W <= 10 ** metrics.log10_bound_lu_prrp(n, b, 2.0)
+    # L(point) L11^-1 recovers the tau-bounded block L of every panel.
+    L = f.L()
+    for k0 in range(0, n - b, b):
+        bw = min(b, n - k0)
+        blk = sla.solve_triangular(L[k0:k0 + bw, k0:k0 + bw].T, L[k0 + bw:, k0:k0 + bw].T,
+                                   lower=False, unit_diagonal=True).T
+        assert np.abs(blk).max() <= 2.0 * (1 + 1e-10)
+
+
+def test_lu_prrp_forced_exchanges_keep_invariants():
+    A = np.random.default_rng(5).standard_normal((96, 96))
+    f = lu.lu_prrp(A, 16, 1.05)
+    assert f.swaps > 0
+    assert f.max_block_L <= 1.05 * TAU_TOL
+    assert metrics.backward_error(A, f.LU, f.perm) <= 1e-14
+
+
+def test_wilkinson_gepp_growth_closed_form():
+    """GEPP on the Wilkinson matrix: growth exactly 2^(n-1) (all entries are
+    exact powers of two)."""
+    n = 60
+    g = lu.gepp(inputs.wilkinson(n))
+    assert g.max_abs_U == 2.0 ** (n - 1)
+
+
+def test_wilkinson_lu_prrp_small_growth():
+    n = 256
+    A = inputs.wilkinson(n)
+    f = lu.lu_prrp(A, 16, 2.0)
+    assert f.g_W < 16.0
+    assert metrics.backward_error(A, f.LU, f.perm) <= 1e-15
+
+
+def test_foster_gepp_growth_closed_form():
+    """Foster (c=1, kh=2/3): GEPP growth (2/3)(2^(n-1) - 1)."""
+    n = 40
+    g = lu.gepp(inputs.foster(n))
+    assert g.max_abs_U == pytest.approx((2.0 / 3.0) * (2.0 ** (n - 1) - 1.0), rel=1e-10)
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(x) for x in line.split()])
+    return rows
+
+
+@pytest.mark.parametrize("b", [32, 64, 128])
+def test_foster_lu_prrp_growth_printed(b):
+    """Table "tab_foster": LU_PRRP on the n=2048 Foster matrix has g_W = 2.66
+    for every panel size (printed to two decimals; the value is 8/3)."""
+    table = {int(r[1]): r[2] for r in _golden("foster_lu_prrp.txt")}
+    f = lu.lu_prrp(inputs.foster(2048), b, 2.0)
+    assert abs(f.g_W - table[b]) < 0.01
+    assert metrics.backward_error(inputs.foster(2048), f.LU, f.perm) < 1e-15
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("b", [8, 16])
+def test_foster_lu_prrp_growth_printed_small_panels(b):
+    table = {int(r[1]): r[2] for r in _golden("foster_lu_prrp.txt")}
+    f = lu.lu_prrp(inputs.foster(2048), b, 2.0)
+    assert abs(f.g_W - table[b]) < 0.01
+
+
+# ------------------------------------------------------------------ CALU_PRRP
+
+def test_tile_bounds():
+    assert lu.tile_bounds(1000, 512, 128) == [(0, 512), (512, 1000)]
+    assert lu.tile_bounds(1100, 512, 128) == [(0, 512), (512, 1100)]   # 76-row rest merged
+    assert lu.tile_bounds(300, 512, 128) == [(0, 300)]
+    with pytest.raises(ValueError):
+        lu.tile_bounds(300, 128, 128)
+
+
+@pytest.mark.parametrize("n,b", [(64, 8), (90, 16)])
+def test_calu_prrp_one_tile_equals_lu_prrp(n, b):
+    A = np.random.default_rng(n + b).standard_normal((n, n))
+    f1 = lu.lu_prrp(A, b, 2.0)
+    f2 = lu.calu_prrp(A, b, 2.0, tile_rows=n + 1)
+    assert list(f1.perm) == list(f2.perm)
+    assert np.allclose(f1.LU, f2.LU, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("tree", ["binary", "flat"])
+@pytest.mark.parametrize("n,b,tr", [(256, 16, 32), (200, 8, 24), (128, 16, 17)])
+def test_calu_prrp_invariants(tree, n, b, tr):
+    A = np.random.default_rng(n * 7 + b).standard_normal((n, n))
+    f = lu.calu_prrp(A, b, 2.0, tile_rows=tr, tree=tree)
+    assert sorted(f.perm) == list(range(n))
+    assert metrics.backward_error(A, f.LU, f.perm) <= 1e-15 * n
+    assert max(f.node_max_M) <= 2.0 * TAU_TOL          # every node is tau-bounded
+    assert f.step_growth_ok                             # (1 + tau b)^(H+1) per step
+    assert f.g_W <= 10 ** metrics.log10_bound_calu_prrp(n, b, 2.0, f.tree_height)
+
+
+def test_calu_prrp_binary_height():
+    n, b, tr = 256, 8, 16
+    A = np.random.default_rng(1).standard_normal((n, n))
+    f = lu.calu_prrp(A, b, 2.0, tile_rows=tr, panels=1)
+    assert f.tree_height == 4          # 16 leaves -> 4 levels
+
+
+@pytest.mark.parametrize("tree", ["binary", "flat"])
+def test_calu_prrp_first_step_is_schur_complement(tree):
+    """Equation "caluprrpequiv": after the first step the trailing matrix is
+    A22 - A21 A11^-1 A12 for the tournament's pivot rows, however the rows
+    were chosen."""
+    n, b = 96, 8
+    A = np.random.default_rng(3).standard_normal((n, n))
+    f = lu.calu_prrp(A, b, 2.0, tile_rows=20, tree=tree, panels=1)
+    P = A[f.perm]
+    S = P[b:, b:] - P[b:, :b] @ np.linalg.solve(P[:b, :b], P[:b, b:])
+    assert np.allclose(f.LU[b:, b:], S, rtol=1e-11, atol=1e-11)
+    # Rows of the first block are the tournament winners.
+    assert set(f.perm[:b]) == set(f.panel_sel[0])
