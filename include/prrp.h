@@ -1,0 +1,147 @@
+/*
+ * prrp.h -- C ABI of the MI355X (gfx950) LU_PRRP / CALU_PRRP library.
+ *
+ * The library factors a dense square matrix as A = Pi L U with panel rank
+ * revealing pivoting (Khabou, Demmel, Grigori, Gu, "LU factorization with
+ * panel rank revealing pivoting and its communication avoiding version"):
+ * every b-column panel chooses its b pivot rows by a strong rank revealing QR
+ * of the panel's transpose (Section 2.1, Algorithm "LU_PRRP factorization";
+ * Appendix A, Algorithm "Strong RRQR"), or, for CALU_PRRP, by a tournament of
+ * strong RRQRs over row tiles of the panel (Section 3.1).
+ *
+ * Conventions shared by every entry point
+ *   - All matrix/vector pointers are DEVICE pointers.  Matrices are row-major
+ *     with a leading dimension (elements between consecutive rows) >= columns.
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL is
+ *     the default stream).  Argument errors are detected on the host before
+ *     anything is enqueued and returned synchronously.
+ *   - The caller owns every buffer.  Factor and solve calls allocate no device
+ *     memory: scratch space comes from a caller-provided `workspace` whose
+ *     size is returned by the matching *_workspace_size query (a pure host
+ *     function that needs no GPU).
+ *   - Return value: 0 = enqueued; -k = argument k invalid (1-based); -1000 - e
+ *     = HIP runtime error e while enqueueing.  Numerical status (singular
+ *     pivot, non-finite data, exchange loop cap) is written by the kernels to
+ *     the device `prrp_stats` record (field `info`).
+ *   - Pivot ties (equal or nearly equal candidates) are broken
+ *     deterministically: magnitudes are compared on their binary64 encoding
+ *     with the 19 low mantissa bits dropped, and the lowest current row index
+ *     wins among equals (for an exchange: lowest row, then lowest slot).
+ *   - Supported sizes: 1 <= n <= 2^19 - 2, 1 <= b <= 128, b <= n.
+ *
+ * Factor output (in place, LAPACK convention): on exit A holds U on and above
+ * the diagonal and the unit-lower L strictly below it (diagonal implied), and
+ * perm[i] is the input row now in position i, i.e. A_in[perm[i], :] =
+ * (L U)[i, :] (the problem statement A = Pi L U of the introduction).
+ */
+#ifndef PRRP_H
+#define PRRP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Reduction tree of the CALU_PRRP tournament (Section 3.1: binary tree; the
+ * flat tree is the sequential variant discussed with its growth bound). */
+typedef enum { PRRP_TREE_BINARY = 0, PRRP_TREE_FLAT = 1 } prrp_tree_kind;
+
+/* Arithmetic of the Schur-complement update A22 -= L21 U12.  The panel, the
+ * pivot selection and the triangular solves are FP64 in every mode; the
+ * trailing matrix stays FP64.  FP32 / BF16 round L21 and U12 to that type and
+ * accumulate their product in FP32 before it is subtracted in FP64. */
+typedef enum { PRRP_FP64 = 0, PRRP_SCHUR_FP32 = 1, PRRP_SCHUR_BF16 = 2 } prrp_precision;
+
+/* Device-resident status and growth record written by a factorization.
+ * g_W = max_abs_W / max_abs_A (growth over all intermediate active matrices
+ * and U, Section 2.2), g_U = max_abs_U / max_abs_A.
+ * info: 0 ok; j > 0: first panel step that met an exactly zero residual or
+ * zero pivot, as a 1-based column (the factors past that column are not
+ * meaningful); -1 non-finite value met; -2 a kernel's bounded wait expired;
+ * -3 the strong RRQR exchange loop reached its cap without meeting tau. */
+typedef struct prrp_stats {
+  double max_abs_A;
+  double max_abs_W;
+  double max_abs_U;
+  double max_block_L;   /* max |(R11^-1 R12)_ij| of the final panel selections */
+  int64_t swaps;        /* strong RRQR interchanges, all panels and tree nodes */
+  int32_t info;
+  int32_t tree_height;  /* CALU_PRRP: height of the tallest tournament */
+  int32_t panels;
+  int32_t reserved[3];
+} prrp_stats;
+
+/* Workspace bytes for prrp_factor / prrp_factor_mixed (method 0) or
+ * calu_prrp_factor (method 1, tile_rows as passed there) on an n x n matrix
+ * with panel width b.  Host-only; returns 0 or -k for an invalid argument. */
+int prrp_workspace_size(int64_t n, int b, int method, int64_t tile_rows, size_t* bytes);
+
+/* LU_PRRP (Section 2.1, Algorithm "LU_PRRP factorization"): in-place factor
+ * of the n x n matrix A (leading dimension lda), panel width b, strong RRQR
+ * threshold tau > 1 (Appendix A).  perm: device int64[n] (output).
+ * stats: device prrp_stats (output, required). */
+int prrp_factor(double* A, int64_t n, int64_t lda, int b, double tau, int64_t* perm,
+                prrp_stats* stats, void* workspace, size_t ws_bytes, void* stream);
+
+/* As prrp_factor with the Schur update in `schur` precision (see
+ * prrp_precision).  Pivots may differ from the FP64 factorization. */
+int prrp_factor_mixed(double* A, int64_t n, int64_t lda, int b, double tau, int64_t* perm,
+                      prrp_stats* stats, void* workspace, size_t ws_bytes, void* stream,
+                      int schur);
+
+/* CALU_PRRP (Section 3.1): tournament pivoting over row tiles of tile_rows
+ * rows (>= b + 1; a last remainder of <= b rows joins the previous tile),
+ * reduced by strong RRQR along a binary or flat tree (`tree`, a
+ * prrp_tree_kind); then the panel is factored with the winners as pivots and
+ * the step continues as in LU_PRRP.  `schur` as in prrp_factor_mixed. */
+int calu_prrp_factor(double* A, int64_t n, int64_t lda, int b, double tau, int tree,
+                     int64_t tile_rows, int64_t* perm, prrp_stats* stats, void* workspace,
+                     size_t ws_bytes, void* stream, int schur);
+
+/* Workspace bytes for prrp_solve / prrp_refine with nrhs right-hand sides. */
+int prrp_solve_workspace_size(int64_t n, int64_t nrhs, size_t* bytes);
+
+/* Solve A X = B with the factors of prrp_factor (introduction: A = Pi L U):
+ * X = U^-1 L^-1 B[perm].  B: n x nrhs row-major (ldb >= nrhs), overwritten by
+ * X.  LU, perm as returned by a factor call. */
+int prrp_solve(const double* LU, int64_t n, int64_t lda, const int64_t* perm, double* B,
+               int64_t nrhs, int64_t ldb, void* workspace, size_t ws_bytes, void* stream);
+
+/* R = B - A X evaluated as if in twice the working precision and rounded
+ * once (error-free TwoProduct by FMA and TwoSum, accumulated as in Ogita,
+ * Rump and Oishi's Dot2).  A: n x n (lda); X, B, R: n x nrhs (ldx). */
+int prrp_residual(const double* A, int64_t n, int64_t lda, const double* X, const double* B,
+                  double* R, int64_t nrhs, int64_t ldx, void* stream);
+
+/* Iterative refinement of the solution of A X = B (used with the paper's
+ * linear-solver experiments): X = solve(B); repeat R = prrp_residual; D =
+ * solve(R); X += D, until max|D| <= tol max|X| per right-hand side, the
+ * correction stops halving, or max_iter corrections.  This call synchronizes
+ * `stream` once per iteration to test convergence.  iters (host, may be
+ * NULL) receives the number of corrections; final_rel (host, may be NULL) the
+ * last max|D|/max|X|. */
+int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const int64_t* perm,
+                const double* B, double* X, int64_t nrhs, int64_t ldx, double tol, int max_iter,
+                int* iters, double* final_rel, void* workspace, size_t ws_bytes, void* stream);
+
+/* C = alpha A B + beta C for row-major FP64 matrices (M x K, K x N, M x N),
+ * computed by the MFMA kernel of the Schur-complement update (equation
+ * "update", Section 2.1).  prec: a prrp_precision; with FP32 / BF16 the
+ * operands are rounded to that type and their products accumulated in FP32,
+ * C stays FP64.  beta == 0 does not read C. */
+int prrp_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+              const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int prec,
+              void* stream);
+
+/* Human-readable text for a return code or an info value. */
+const char* prrp_status_string(int code);
+
+/* Library version string. */
+const char* prrp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRRP_H */

@@ -1,0 +1,176 @@
+"""LU_PRRP / CALU_PRRP on MI355X (gfx950).
+
+Thin torch-facing wrappers over the C ABI of libprrp.so (include/prrp.h).
+Matrices are CUDA (HIP) float64 tensors, row-major; factorizations run in
+place on the caller's stream.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+__all__ = ["factor", "calu_factor", "solve", "residual", "refine", "gemm", "FactorResult",
+           "read_stats"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check_matrix(A, name="A"):
+    torch = _torch()
+    if not isinstance(A, torch.Tensor) or A.device.type != "cuda":
+        raise ValueError("%s must be a CUDA tensor" % name)
+    if A.dtype != torch.float64:
+        raise ValueError("%s must be float64" % name)
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("%s must be 2-D with unit column stride (row-major)" % name)
+
+
+@dataclass
+class FactorResult:
+    perm: object        # torch int64 [n] on the device
+    stats_raw: object   # torch uint8 [sizeof prrp_stats] on the device
+    workspace: object
+
+    def stats(self) -> dict:
+        return read_stats(self.stats_raw)
+
+
+def read_stats(raw) -> dict:
+    from ._lib import Stats
+    host = raw.cpu().numpy().tobytes()
+    s = Stats.from_buffer_copy(host)
+    return dict(max_abs_A=s.max_abs_A, max_abs_W=s.max_abs_W, max_abs_U=s.max_abs_U,
+                max_block_L=s.max_block_L, swaps=int(s.swaps), info=int(s.info),
+                tree_height=int(s.tree_height),
+                g_W=(s.max_abs_W / s.max_abs_A) if s.max_abs_A > 0 else float("nan"),
+                g_U=(s.max_abs_U / s.max_abs_A) if s.max_abs_A > 0 else float("nan"))
+
+
+def _alloc(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def factor(A, b: int, tau: float = 2.0, precision: str = "fp64", workspace=None) -> FactorResult:
+    """LU_PRRP of A in place (A = Pi L U; A[perm] = L U on exit)."""
+    from . import _lib
+    torch = _torch()
+    _check_matrix(A)
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    ws_bytes = _lib.workspace_size(n, b, 0, 0)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc(ws_bytes, A.device)
+    perm = torch.empty(n, dtype=torch.int64, device=A.device)
+    stats = torch.zeros(_lib.STATS_BYTES, dtype=torch.uint8, device=A.device)
+    code = _lib.lib().prrp_factor_mixed(A.data_ptr(), n, A.stride(0), b, float(tau), perm.data_ptr(),
+                                        stats.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                        _stream_ptr(), _lib.PRECISIONS[precision])
+    _lib.check(code, "prrp_factor_mixed")
+    return FactorResult(perm, stats, workspace)
+
+
+def calu_factor(A, b: int, tau: float = 2.0, tree: str = "binary", tile_rows: int = 512,
+                precision: str = "fp64", workspace=None) -> FactorResult:
+    """CALU_PRRP of A in place with tournament pivoting over row tiles."""
+    from . import _lib
+    torch = _torch()
+    _check_matrix(A)
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    ws_bytes = _lib.workspace_size(n, b, 1, tile_rows)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc(ws_bytes, A.device)
+    perm = torch.empty(n, dtype=torch.int64, device=A.device)
+    stats = torch.zeros(_lib.STATS_BYTES, dtype=torch.uint8, device=A.device)
+    code = _lib.lib().calu_prrp_factor(A.data_ptr(), n, A.stride(0), b, float(tau), _lib.TREES[tree],
+                                       tile_rows, perm.data_ptr(), stats.data_ptr(),
+                                       workspace.data_ptr(), workspace.numel(), _stream_ptr(),
+                                       _lib.PRECISIONS[precision])
+    _lib.check(code, "calu_prrp_factor")
+    return FactorResult(perm, stats, workspace)
+
+
+def solve(LU, perm, B, workspace=None):
+    """X = U^-1 L^-1 B[perm]; returns a new tensor (B is not modified)."""
+    from . import _lib
+    _check_matrix(LU, "LU")
+    n = LU.shape[0]
+    X = B.clone().contiguous()
+    if X.dim() == 1:
+        X = X.view(n, 1)
+    nrhs = X.shape[1]
+    ws_bytes = _lib.solve_workspace_size(n, nrhs)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc(ws_bytes, LU.device)
+    code = _lib.lib().prrp_solve(LU.data_ptr(), n, LU.stride(0), perm.data_ptr(), X.data_ptr(), nrhs,
+                                 X.stride(0), workspace.data_ptr(), workspace.numel(), _stream_ptr())
+    _lib.check(code, "prrp_solve")
+    return X.view(B.shape)
+
+
+def residual(A, X, B):
+    """R = B - A X with a doubled-precision accumulation (rounded once)."""
+    from . import _lib
+    torch = _torch()
+    _check_matrix(A)
+    n = A.shape[0]
+    X2 = X.contiguous().view(n, -1)
+    B2 = B.contiguous().view(n, -1)
+    R = torch.empty_like(X2)
+    code = _lib.lib().prrp_residual(A.data_ptr(), n, A.stride(0), X2.data_ptr(), B2.data_ptr(),
+                                    R.data_ptr(), X2.shape[1], X2.stride(0), _stream_ptr())
+    _lib.check(code, "prrp_residual")
+    return R.view(B.shape)
+
+
+def refine(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30, workspace=None):
+    """Iterative refinement; returns (X, iterations, last max|dX|/max|X|)."""
+    import ctypes
+    from . import _lib
+    torch = _torch()
+    _check_matrix(A)
+    n = A.shape[0]
+    B2 = B.contiguous().view(n, -1)
+    nrhs = B2.shape[1]
+    X = torch.empty_like(B2)
+    ws_bytes = _lib.solve_workspace_size(n, nrhs)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc(ws_bytes, A.device)
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    code = _lib.lib().prrp_refine(A.data_ptr(), LU.data_ptr(), n, A.stride(0), perm.data_ptr(),
+                                  B2.data_ptr(), X.data_ptr(), nrhs, nrhs, float(tol), int(max_iter),
+                                  ctypes.byref(it), ctypes.byref(rel), workspace.data_ptr(),
+                                  workspace.numel(), _stream_ptr())
+    _lib.check(code, "prrp_refine")
+    return X.view(B.shape), it.value, rel.value
+
+
+def gemm(A, B, C=None, alpha: float = 1.0, beta: float = 0.0, precision: str = "fp64"):
+    """C = alpha A B + beta C with the library's MFMA kernel (row-major float64)."""
+    from . import _lib
+    torch = _torch()
+    for t, nm in ((A, "A"), (B, "B")):
+        _check_matrix(t, nm)
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K:
+        raise ValueError("inner dimensions differ")
+    if C is None:
+        C = torch.zeros(M, N, dtype=torch.float64, device=A.device)
+    _check_matrix(C, "C")
+    code = _lib.lib().prrp_gemm(M, N, K, float(alpha), A.data_ptr(), A.stride(0), B.data_ptr(),
+                                B.stride(0), float(beta), C.data_ptr(), C.stride(0),
+                                _lib.PRECISIONS[precision], _stream_ptr())
+    _lib.check(code, "prrp_gemm")
+    return C

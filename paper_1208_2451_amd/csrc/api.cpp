@@ -1,0 +1,552 @@
+// Host driver and C ABI of the gfx950 LU_PRRP / CALU_PRRP library.
+//
+// prrp_factor runs Algorithm "LU_PRRP factorization" (Section 2.1) one panel
+// at a time on one stream:
+//   srrqr  -- strong RRQR of the panel transpose (pivot rows, M = R11^-1 R12)
+//   gepp   -- transposition plan, GEPP of the b x b block, Pi11 L11, L11^-1
+//   moves  -- the row interchanges applied to the columns outside the panel
+//   gemm   -- L21 = M^T (Pi11 L11), U12 = L11^-1 A12, A22 -= L21 U12
+// calu_prrp_factor replaces the srrqr step by a tournament (Section 3.1):
+// strong RRQR of every row tile, then of stacked candidate pairs up a binary
+// tree (or along a chain), and finally the QR with the winners as pivots.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "prrp.h"
+
+using namespace prrp;
+
+namespace {
+
+constexpr int kRoundsMax = kMaxB + kMaxExchange + 2;
+constexpr int kRowsPerWgMax = 128;   // 32 row groups x 4 rows per thread
+
+inline uint64_t tau_bits(double tau) {
+  uint64_t u;
+  std::memcpy(&u, &tau, sizeof u);
+  return u >> kDropBits;
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+struct Tiles {
+  std::vector<int> start, len;
+};
+
+// Top-down tiles of tile_rows rows; a last remainder of <= b rows joins the
+// previous tile.
+Tiles tile_bounds(int64_t m, int64_t tile_rows, int b) {
+  Tiles t;
+  for (int64_t s = 0; s < m; s += tile_rows) {
+    t.start.push_back((int)s);
+    t.len.push_back((int)std::min<int64_t>(tile_rows, m - s));
+  }
+  if (t.start.size() > 1 && t.len.back() <= b) {
+    t.len[t.len.size() - 2] += t.len.back();
+    t.start.pop_back();
+    t.len.pop_back();
+  }
+  return t;
+}
+
+// Workgroups per tile so that a tile's rows fit the register budget (at most
+// 128 rows per workgroup) and no workgroup is left without rows.
+int groups_for_rows(int64_t rows, int cap) {
+  int G = (int)std::min<int64_t>(cap, (rows + 31) / 32);
+  if (G < 1) G = 1;
+  while ((rows + G - 1) / G > kRowsPerWgMax) ++G;
+  const int64_t rpw = (rows + G - 1) / G;
+  return (int)std::max<int64_t>(1, (rows + rpw - 1) / rpw);
+}
+
+struct Layout {
+  size_t slots_set_words = 0;     // words per slot set
+  size_t off_slots = 0, off_rounds = 0, off_abort = 0, off_sel = 0, off_lists = 0;
+  size_t off_y = 0, off_pl = 0, off_linv = 0, off_moves = 0, off_lsel = 0;
+  size_t total = 0;
+  int max_members = 0;            // sum over groups of workgroups in any launch
+  int max_groups = 0;
+};
+
+Layout make_layout(int64_t n, int b, int method, int64_t tile_rows) {
+  Layout L;
+  const int cap = std::min(256, device_cus());
+  int members = groups_for_rows(n, cap);
+  int groups = 1;
+  if (method == 1) {
+    const int64_t ntiles = (n + tile_rows - 1) / tile_rows;
+    const int Gl = groups_for_rows(std::min<int64_t>(tile_rows + b, n), cap);
+    members = std::max<int64_t>(members, ntiles * Gl);
+    members = std::max<int64_t>(members, ((ntiles + 1) / 2) * groups_for_rows(2 * b, cap));
+    members = std::max<int>(members, groups_for_rows(tile_rows + b + b, cap));
+    groups = (int)std::max<int64_t>(1, ntiles);
+  }
+  L.max_members = members;
+  L.max_groups = groups;
+  L.slots_set_words = (size_t)members * kRoundsMax * kPostW;
+  size_t off = 0;
+  L.off_slots = off;  off += align_up(2 * L.slots_set_words * 8, 256);
+  L.off_rounds = off; off += align_up(2 * (size_t)groups * 4 + 16, 256);
+  L.off_abort = off;  off += 256;
+  L.off_sel = off;    off += align_up((size_t)groups * kMaxB * 4, 256);
+  L.off_lsel = off;   off += align_up((size_t)2 * groups * kMaxB * 4, 256);
+  L.off_lists = off;  off += align_up((size_t)groups * (2 * kMaxB + (size_t)tile_rows + 64) * 4 + 64, 256);
+  L.off_y = off;      off += align_up((size_t)n * b * 8, 256);
+  L.off_pl = off;     off += align_up((size_t)b * b * 8, 256);
+  L.off_linv = off;   off += align_up((size_t)b * b * 8, 256);
+  L.off_moves = off;  off += align_up((size_t)(4 * kMaxB + 4) * 4, 256);
+  L.total = off;
+  return L;
+}
+
+inline int herr(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
+#define PRRP_TRY(x)                                   \
+  do {                                                \
+    hipError_t e_ = (x);                              \
+    if (e_ != hipSuccess) return herr(e_);            \
+  } while (0)
+
+struct Ctx {
+  double* A;
+  int64_t n, lda;
+  int b;
+  double tau;
+  int64_t* perm;
+  prrp_stats* stats;
+  char* ws;
+  Layout L;
+  hipStream_t st;
+  int schur;
+  // slot bookkeeping across srrqr launches
+  int launch_no = 0;
+  uint64_t* prev_base = nullptr;
+  size_t prev_group_stride = 0;
+  int prev_ngroups = 0, prev_G = 0, prev_bw = 0;
+  int32_t* prev_rounds = nullptr;
+  int cap = 256;
+
+  uint64_t* slot_set(int parity) {
+    return reinterpret_cast<uint64_t*>(ws + L.off_slots) + (size_t)parity * L.slots_set_words;
+  }
+  int32_t* rounds(int parity) {
+    return reinterpret_cast<int32_t*>(ws + L.off_rounds) + (size_t)parity * L.max_groups;
+  }
+  uint32_t* abort_flag() { return reinterpret_cast<uint32_t*>(ws + L.off_abort); }
+  int32_t* sel() { return reinterpret_cast<int32_t*>(ws + L.off_sel); }
+  int32_t* lsel() { return reinterpret_cast<int32_t*>(ws + L.off_lsel); }
+  int32_t* lists() { return reinterpret_cast<int32_t*>(ws + L.off_lists); }
+  double* Y() { return reinterpret_cast<double*>(ws + L.off_y); }
+  double* PL() { return reinterpret_cast<double*>(ws + L.off_pl); }
+  double* Linv() { return reinterpret_cast<double*>(ws + L.off_linv); }
+  int32_t* mv() { return reinterpret_cast<int32_t*>(ws + L.off_moves); }
+
+  // One srrqr launch; fills in the slot-set bookkeeping.
+  hipError_t srrqr(SrrqrArgs& a) {
+    const int parity = launch_no & 1;
+    a.slots = slot_set(parity);
+    a.group_stride = (size_t)kRoundsMax * a.G * kPostW;
+    a.rounds_out = rounds(parity);
+    a.clear_base = prev_base;
+    a.clear_group_stride = prev_group_stride;
+    a.clear_ngroups = prev_ngroups;
+    a.clear_G = prev_G;
+    a.clear_bw = prev_bw;
+    a.clear_rounds = prev_rounds;
+    a.stats = stats;
+    a.abort_flag = abort_flag();
+    a.tau_bits = tau_bits(tau);
+    hipError_t e = launch_srrqr(a, st);
+    prev_base = a.slots;
+    prev_group_stride = a.group_stride;
+    prev_ngroups = a.ngroups;
+    prev_G = a.G;
+    prev_bw = a.bw;
+    prev_rounds = a.rounds_out;
+    ++launch_no;
+    return e;
+  }
+
+  // Steps after the pivot rows of the panel at k0 are known (sel(), Y()).
+  hipError_t finish_panel(int64_t k0, int bw) {
+    const int64_t m = n - k0;
+    int32_t* mv_dst = mv();
+    int32_t* mv_src = mv() + 2 * kMaxB;
+    int32_t* n_moves = mv() + 4 * kMaxB;
+    GeppArgs ga{A, lda, k0, bw, (int)m, sel(), PL(), Linv(), mv_dst, mv_src, n_moves, stats};
+    hipError_t e = launch_gepp(ga, st);
+    if (e != hipSuccess) return e;
+    MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, (m > bw) ? Y() : nullptr, b};
+    e = launch_moves(ma, st);
+    if (e != hipSuccess) return e;
+    if (m > bw) {
+      // L21 = M^T (Pi11 L11)
+      GemmArgs l21{(int)(m - bw), bw, bw, Y() + (size_t)bw * b, b, PL(), bw,
+                   A + (k0 + bw) * lda + k0, lda, 1.0, 0.0, nullptr, nullptr, PRRP_FP64};
+      e = launch_gemm(l21, st);
+      if (e != hipSuccess) return e;
+      const int64_t nr = n - k0 - bw;
+      double* a12 = A + k0 * lda + k0 + bw;
+      GemmArgs u12{bw, (int)nr, bw, Linv(), bw, a12, lda, a12, lda, 1.0, 0.0,
+                   &stats->max_abs_U, &stats->max_abs_W, PRRP_FP64};
+      e = launch_gemm(u12, st);
+      if (e != hipSuccess) return e;
+      GemmArgs sc{(int)(m - bw), (int)nr, bw, A + (k0 + bw) * lda + k0, lda, a12, lda,
+                  A + (k0 + bw) * lda + k0 + bw, lda, -1.0, 1.0, &stats->max_abs_W, nullptr, schur};
+      e = launch_gemm(sc, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+};
+
+SrrqrArgs base_args(Ctx& c, int64_t k0, int bw) {
+  SrrqrArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.A = c.A;
+  a.lda = c.lda;
+  a.k0 = k0;
+  a.bw = bw;
+  a.ldy = c.b;
+  return a;
+}
+
+int validate_common(double* A, int64_t n, int64_t lda, int b, double tau, int64_t* perm,
+                    prrp_stats* stats, void* ws) {
+  if (!A) return -1;
+  if (n < 1 || n > kMaxN) return -2;
+  if (lda < n) return -3;
+  if (b < 1 || b > kMaxB || b > n) return -4;
+  if (!(tau > 1.0) || !std::isfinite(tau)) return -5;
+  if (!perm) return -6;
+  if (!stats) return -7;
+  if (!ws) return -8;
+  return 0;
+}
+
+int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau, int tree,
+               int64_t tile_rows, int64_t* perm, prrp_stats* stats, void* workspace,
+               size_t ws_bytes, void* stream, int schur) {
+  Ctx c;
+  c.A = A; c.n = n; c.lda = lda; c.b = b; c.tau = tau; c.perm = perm; c.stats = stats;
+  c.ws = static_cast<char*>(workspace);
+  c.st = static_cast<hipStream_t>(stream);
+  c.schur = schur;
+  c.cap = std::min(256, device_cus());
+  c.L = make_layout(n, b, method, tile_rows);
+  PRRP_TRY(srrqr_prepare());
+  PRRP_TRY(launch_init_factor(A, n, lda, perm, stats, c.abort_flag(), c.st));
+  PRRP_TRY(launch_fill_u64(c.slot_set(0), 2 * c.L.slots_set_words, kKeySent, c.st));
+
+  for (int64_t k0 = 0; k0 < n; k0 += b) {
+    const int bw = (int)std::min<int64_t>(b, n - k0);
+    const int64_t m = n - k0;
+    Tiles t;
+    if (method == 1) t = tile_bounds(m, tile_rows, bw);
+    if (method == 0 || t.start.size() == 1) {
+      SrrqrArgs a = base_args(c, k0, bw);
+      a.ngroups = 1;
+      a.G = groups_for_rows(m, c.cap);
+      a.rpw = (int)((m + a.G - 1) / a.G);
+      a.tile_start[0] = 0;
+      a.tile_len[0] = (int)m;
+      a.mode = 0;
+      a.report_rank = 1;
+      a.record_block_L = 1;
+      a.sel_out = c.sel();
+      a.Y = (m > bw) ? c.Y() : nullptr;
+      PRRP_TRY(c.srrqr(a));
+    } else {
+      // ---------------------------------------------- tournament (Sec. 3.1)
+      const int ntiles = (int)t.start.size();
+      if (ntiles > kMaxGroups) return -9;
+      int maxlen = 0;
+      for (int l : t.len) maxlen = std::max(maxlen, l);
+      int32_t* cur = c.lsel();        // candidate sets of the current level
+      int32_t* nxt = c.lsel() + (size_t)c.L.max_groups * kMaxB;
+      int32_t* lists = c.lists();
+      if (tree == PRRP_TREE_BINARY) {
+        SrrqrArgs a = base_args(c, k0, bw);
+        a.ngroups = ntiles;
+        a.G = groups_for_rows(maxlen, c.cap);
+        a.rpw = (maxlen + a.G - 1) / a.G;
+        for (int i = 0; i < ntiles; ++i) { a.tile_start[i] = t.start[i]; a.tile_len[i] = t.len[i]; }
+        a.mode = 0;
+        a.sel_out = cur;
+        PRRP_TRY(c.srrqr(a));
+        int level = ntiles;
+        while (level > 1) {
+          const int pairs = level / 2;
+          // lists of stacked pairs; an odd last node is promoted into cur[pairs]
+          PRRP_TRY(launch_build_lists(cur, level, bw, lists, nxt, pairs, -1, 0, c.st));
+          SrrqrArgs nd = base_args(c, k0, bw);
+          nd.ngroups = pairs;
+          nd.G = groups_for_rows(2 * bw, c.cap);
+          nd.rpw = (2 * bw + nd.G - 1) / nd.G;
+          for (int i = 0; i < pairs; ++i) { nd.tile_start[i] = i * 2 * bw; nd.tile_len[i] = 2 * bw; }
+          nd.row_list = lists;
+          nd.mode = 0;
+          nd.sel_out = nxt;
+          PRRP_TRY(c.srrqr(nd));
+          level = pairs + (level & 1);
+          std::swap(cur, nxt);
+        }
+      } else {
+        // flat tree: running candidates stacked over each next whole tile
+        SrrqrArgs a = base_args(c, k0, bw);
+        a.ngroups = 1;
+        a.G = groups_for_rows(t.len[0], c.cap);
+        a.rpw = (t.len[0] + a.G - 1) / a.G;
+        a.tile_start[0] = t.start[0];
+        a.tile_len[0] = t.len[0];
+        a.mode = 0;
+        a.sel_out = cur;
+        PRRP_TRY(c.srrqr(a));
+        for (int i = 1; i < ntiles; ++i) {
+          PRRP_TRY(launch_build_lists(cur, 1, bw, lists, nullptr, 1, t.start[i], t.len[i], c.st));
+          SrrqrArgs nd = base_args(c, k0, bw);
+          const int len = bw + t.len[i];
+          nd.ngroups = 1;
+          nd.G = groups_for_rows(len, c.cap);
+          nd.rpw = (len + nd.G - 1) / nd.G;
+          nd.tile_start[0] = 0;
+          nd.tile_len[0] = len;
+          nd.row_list = lists;
+          nd.mode = 0;
+          nd.sel_out = nxt;
+          PRRP_TRY(c.srrqr(nd));
+          std::swap(cur, nxt);
+        }
+      }
+      // QR of the panel transpose with the winners as pivots (emits M)
+      SrrqrArgs r = base_args(c, k0, bw);
+      r.ngroups = 1;
+      r.G = groups_for_rows(m, c.cap);
+      r.rpw = (int)((m + r.G - 1) / r.G);
+      r.tile_start[0] = 0;
+      r.tile_len[0] = (int)m;
+      r.mode = 1;
+      r.sel_in = cur;
+      r.record_block_L = 1;
+      r.sel_out = c.sel();
+      r.Y = c.Y();
+      PRRP_TRY(c.srrqr(r));
+    }
+    PRRP_TRY(c.finish_panel(k0, bw));
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* prrp_version(void) { return "prrp-gfx950 0.1"; }
+
+const char* prrp_status_string(int code) {
+  switch (code) {
+    case 0: return "success";
+    case -1: return "invalid argument 1 (matrix pointer) / info: non-finite value";
+    case -2: return "invalid argument 2 (n) / info: bounded wait expired";
+    case -3: return "invalid argument 3 (leading dimension) / info: exchange cap reached";
+    case -4: return "invalid argument 4 (panel width b)";
+    case -5: return "invalid argument 5 (tau must be finite and > 1)";
+    default: break;
+  }
+  if (code <= -1000) return "HIP runtime error while enqueueing";
+  if (code < 0) return "invalid argument";
+  return "singular: exactly zero residual or pivot at this 1-based column";
+}
+
+int prrp_workspace_size(int64_t n, int b, int method, int64_t tile_rows, size_t* bytes) {
+  if (n < 1 || n > kMaxN) return -1;
+  if (b < 1 || b > kMaxB || b > n) return -2;
+  if (method != 0 && method != 1) return -3;
+  if (method == 1 && (tile_rows < b + 1)) return -4;
+  if (!bytes) return -5;
+  *bytes = make_layout(n, b, method, method == 1 ? tile_rows : 0).total;
+  return 0;
+}
+
+int prrp_factor(double* A, int64_t n, int64_t lda, int b, double tau, int64_t* perm,
+                prrp_stats* stats, void* workspace, size_t ws_bytes, void* stream) {
+  return prrp_factor_mixed(A, n, lda, b, tau, perm, stats, workspace, ws_bytes, stream, PRRP_FP64);
+}
+
+int prrp_factor_mixed(double* A, int64_t n, int64_t lda, int b, double tau, int64_t* perm,
+                      prrp_stats* stats, void* workspace, size_t ws_bytes, void* stream,
+                      int schur) {
+  int v = validate_common(A, n, lda, b, tau, perm, stats, workspace);
+  if (v) return v;
+  if (ws_bytes < make_layout(n, b, 0, 0).total) return -9;
+  if (schur < 0 || schur > 2) return -11;
+  return run_factor(0, A, n, lda, b, tau, 0, 0, perm, stats, workspace, ws_bytes, stream, schur);
+}
+
+int calu_prrp_factor(double* A, int64_t n, int64_t lda, int b, double tau, int tree,
+                     int64_t tile_rows, int64_t* perm, prrp_stats* stats, void* workspace,
+                     size_t ws_bytes, void* stream, int schur) {
+  if (!A) return -1;
+  if (n < 1 || n > kMaxN) return -2;
+  if (lda < n) return -3;
+  if (b < 1 || b > kMaxB || b > n) return -4;
+  if (!(tau > 1.0) || !std::isfinite(tau)) return -5;
+  if (tree != PRRP_TREE_BINARY && tree != PRRP_TREE_FLAT) return -6;
+  if (tile_rows < b + 1) return -7;
+  if (!perm) return -8;
+  if (!stats) return -9;
+  if (!workspace) return -10;
+  if (ws_bytes < make_layout(n, b, 1, tile_rows).total) return -11;
+  if (schur < 0 || schur > 2) return -13;
+  if ((n + tile_rows - 1) / tile_rows > kMaxGroups) return -7;
+  return run_factor(1, A, n, lda, b, tau, tree, tile_rows, perm, stats, workspace, ws_bytes,
+                    stream, schur);
+}
+
+int prrp_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+              const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int prec,
+              void* stream) {
+  if (M < 0 || M > INT32_MAX) return -1;
+  if (N < 0 || N > INT32_MAX) return -2;
+  if (K < 0 || K > INT32_MAX) return -3;
+  if (!A && M > 0 && K > 0) return -5;
+  if (lda < K) return -6;
+  if (!B && K > 0 && N > 0) return -7;
+  if (ldb < N) return -8;
+  if (!C && M > 0 && N > 0) return -10;
+  if (ldc < N) return -11;
+  if (prec < 0 || prec > 2) return -12;
+  GemmArgs g{(int)M, (int)N, (int)K, A, lda, B, ldb, C, ldc, alpha, beta, nullptr, nullptr, prec};
+  return herr(launch_gemm(g, static_cast<hipStream_t>(stream)));
+}
+
+// ------------------------------------------------------------------ solves
+int prrp_solve_workspace_size(int64_t n, int64_t nrhs, size_t* bytes) {
+  if (n < 1 || n > kMaxN) return -1;
+  if (nrhs < 1) return -2;
+  if (!bytes) return -3;
+  const int64_t nb = (n + 63) / 64;
+  // flags + ticket | two n x nrhs vectors (refinement) | 2 nrhs maxima
+  *bytes = align_up((size_t)(nb + 8) * 8, 256) + 2 * align_up((size_t)n * nrhs * 8, 256) +
+           align_up((size_t)nrhs * 16 + 16, 256);
+  return 0;
+}
+
+namespace {
+int solve_impl(const double* LU, int64_t n, int64_t lda, const int64_t* perm, const double* Bsrc,
+               int64_t ldb, double* X, int64_t nrhs, int64_t ldx, char* ws, hipStream_t st) {
+  const int64_t nb = (n + 63) / 64;
+  uint64_t* flags = reinterpret_cast<uint64_t*>(ws);
+  uint32_t* ticket = reinterpret_cast<uint32_t*>(flags + nb);
+  double* tmp = reinterpret_cast<double*>(ws + align_up((size_t)(nb + 8) * 8, 256));
+  // X = B[perm]
+  PRRP_TRY(launch_gather_rows(Bsrc, ldb, perm, tmp, nrhs, n, nrhs, st));
+  PRRP_TRY(launch_fill_u64(flags, (size_t)nb + 8, 0ull, st));
+  PRRP_TRY(launch_trsv_blocked(LU, n, lda, tmp, nrhs, nrhs, 1, flags, ticket, 1u, st));
+  PRRP_TRY(launch_fill_u64(flags, (size_t)nb + 8, 0ull, st));
+  PRRP_TRY(launch_trsv_blocked(LU, n, lda, tmp, nrhs, nrhs, 0, flags, ticket, 1u, st));
+  // copy out (row strides may differ)
+  PRRP_TRY(hipMemcpy2DAsync(X, ldx * 8, tmp, nrhs * 8, nrhs * 8, n, hipMemcpyDeviceToDevice, st));
+  return 0;
+}
+}  // namespace
+
+int prrp_solve(const double* LU, int64_t n, int64_t lda, const int64_t* perm, double* B,
+               int64_t nrhs, int64_t ldb, void* workspace, size_t ws_bytes, void* stream) {
+  if (!LU) return -1;
+  if (n < 1 || n > kMaxN) return -2;
+  if (lda < n) return -3;
+  if (!perm) return -4;
+  if (!B) return -5;
+  if (nrhs < 1) return -6;
+  if (ldb < nrhs) return -7;
+  size_t need = 0;
+  prrp_solve_workspace_size(n, nrhs, &need);
+  if (!workspace) return -8;
+  if (ws_bytes < need) return -9;
+  return solve_impl(LU, n, lda, perm, B, ldb, B, nrhs, ldb, static_cast<char*>(workspace),
+                    static_cast<hipStream_t>(stream));
+}
+
+int prrp_residual(const double* A, int64_t n, int64_t lda, const double* X, const double* B,
+                  double* R, int64_t nrhs, int64_t ldx, void* stream) {
+  if (!A) return -1;
+  if (n < 1 || n > kMaxN) return -2;
+  if (lda < n) return -3;
+  if (!X) return -4;
+  if (!B) return -5;
+  if (!R) return -6;
+  if (nrhs < 1) return -7;
+  if (ldx < nrhs) return -8;
+  return herr(launch_residual(A, n, lda, X, ldx, B, ldx, R, ldx, nrhs,
+                              static_cast<hipStream_t>(stream)));
+}
+
+int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const int64_t* perm,
+                const double* B, double* X, int64_t nrhs, int64_t ldx, double tol, int max_iter,
+                int* iters, double* final_rel, void* workspace, size_t ws_bytes, void* stream) {
+  if (!A) return -1;
+  if (!LU) return -2;
+  if (n < 1 || n > kMaxN) return -3;
+  if (lda < n) return -4;
+  if (!perm) return -5;
+  if (!B) return -6;
+  if (!X) return -7;
+  if (nrhs < 1) return -8;
+  if (ldx < nrhs) return -9;
+  if (!(tol >= 0.0)) return -10;
+  if (max_iter < 0) return -11;
+  size_t need = 0;
+  prrp_solve_workspace_size(n, nrhs, &need);
+  if (!workspace) return -15;
+  if (ws_bytes < need) return -16;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const int64_t nb = (n + 63) / 64;
+  size_t off = align_up((size_t)(nb + 8) * 8, 256);
+  double* R = reinterpret_cast<double*>(ws + off + align_up((size_t)n * nrhs * 8, 256));
+  double* mx = reinterpret_cast<double*>(ws + off + 2 * align_up((size_t)n * nrhs * 8, 256));
+  int rc = solve_impl(LU, n, lda, perm, B, ldx, X, nrhs, ldx, ws, st);
+  if (rc) return rc;
+  std::vector<double> h(2 * nrhs);
+  double prev = INFINITY;
+  int it = 0;
+  double rel = INFINITY;
+  for (it = 1; it <= max_iter; ++it) {
+    PRRP_TRY(launch_residual(A, n, lda, X, ldx, B, ldx, R, nrhs, nrhs, st));
+    rc = solve_impl(LU, n, lda, perm, R, nrhs, R, nrhs, nrhs, ws, st);
+    if (rc) return rc;
+    PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(mx), 2 * nrhs, 0ull, st));
+    PRRP_TRY(launch_axpy_maxrel(X, ldx, R, nrhs, n, nrhs, mx, st));
+    PRRP_TRY(hipMemcpyAsync(h.data(), mx, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    PRRP_TRY(hipStreamSynchronize(st));
+    rel = 0.0;
+    for (int64_t r = 0; r < nrhs; ++r) {
+      const double xm = h[2 * r + 1] > 0.0 ? h[2 * r + 1] : 1.0;
+      rel = std::max(rel, h[2 * r] / xm);
+    }
+    if (!(rel > tol) || rel > 0.5 * prev) break;
+    prev = rel;
+  }
+  if (iters) *iters = std::min(it, max_iter);
+  if (final_rel) *final_rel = rel;
+  return 0;
+}
+
+}  // extern "C"

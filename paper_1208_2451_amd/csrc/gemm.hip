@@ -1,0 +1,217 @@
+// Tiled MFMA GEMM for gfx950: C = alpha * A * B + beta * C (row-major).
+//
+// Used for the Schur-complement update A22 -= L21 U12 (equation "update" of
+// Section 2.1, which carries nearly all of the 2n^3/3 flops, Appendix C) and
+// for the two triangular solves of a panel step, written as products with
+// explicitly formed b x b factors (L21 = M^T (Pi11 L11), U12 = L11^-1 A12).
+//
+// Tile 128 x 128 per workgroup of 4 waves (2 x 2 waves of 64 x 64), K staged
+// through LDS 16 deep with the next K-slab prefetched into registers while the
+// current one is multiplied.  FP64 uses v_mfma_f64_16x16x4f64; the reduced
+// precision Schur variants round the FP64 operands to FP32 or BF16 on their
+// way into LDS and use v_mfma_f32_16x16x4f32 / v_mfma_f32_16x16x32_bf16 with
+// FP32 accumulation; C stays FP64.
+//
+// MFMA 16x16 operand layout (wave64): A operand lane l holds A[l%16][k-group
+// l/16], B operand lane l holds B[k-group l/16][l%16].  The 4 accumulator
+// values of lane l are D[4*(l/16) + v][l%16] for the FP32-accumulating
+// instructions but D[l/16 + 4*v][l%16] for v_mfma_f64_16x16x4f64 (measured
+// with a one-wave probe on gfx950).
+#include "common.h"
+#include "kernels.h"
+
+namespace prrp {
+
+namespace {
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int kGemmThreads = 256;
+constexpr int APAD = 4;   // LDS row padding (elements)
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  // round to nearest even
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+template <typename T> struct Lds;
+template <> struct Lds<double> { typedef double type; };
+template <> struct Lds<float> { typedef float type; };
+template <> struct Lds<unsigned short> { typedef unsigned short type; };
+
+template <typename T> __device__ __forceinline__ T conv(double v);
+template <> __device__ __forceinline__ double conv<double>(double v) { return v; }
+template <> __device__ __forceinline__ float conv<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ unsigned short conv<unsigned short>(double v) {
+  return f2bf((float)v);
+}
+}  // namespace
+
+// T: LDS/operand element type (double, float, bf16 as unsigned short).
+template <typename T>
+__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
+  // bf16 needs K multiples of 32 per MFMA; stage 32-deep slabs for it
+  constexpr int KS = (sizeof(T) == 2) ? 32 : BK;
+  __shared__ T As[2][KS][BM + APAD];
+  __shared__ T Bs[2][KS][BN + APAD];
+  __shared__ double red[4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * BM;
+  const int n0 = blockIdx.x * BN;
+  const int M = g.M, N = g.N, K = g.K;
+
+  // global -> register staging: each thread holds KS*BM/256 A and KS*BN/256 B values
+  constexpr int AV = KS * BM / kGemmThreads;   // 8 (or 16 for bf16)
+  constexpr int BV = KS * BN / kGemmThreads;
+  double ra[AV], rb[BV];
+  // A: thread -> row (tid % BM... ) use: row = tid >> 1, k-chunk = (tid & 1) * AV
+  const int a_row = tid >> 1, a_k = (tid & 1) * AV;
+  const int b_k = tid / (BN / BV), b_n = (tid % (BN / BV)) * BV;
+
+  auto load_slab = [&](int k0) {
+    const int gr = m0 + a_row;
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int gk = k0 + a_k + v;
+      ra[v] = (gr < M && gk < K) ? g.A[(int64_t)gr * g.lda + gk] : 0.0;
+    }
+    const int gk = k0 + b_k;
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int gc = n0 + b_n + v;
+      rb[v] = (gk < K && gc < N) ? g.B[(int64_t)gk * g.ldb + gc] : 0.0;
+    }
+  };
+  auto store_slab = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) As[buf][a_k + v][a_row] = conv<T>(ra[v]);
+#pragma unroll
+    for (int v = 0; v < BV; ++v) Bs[buf][b_k][b_n + v] = conv<T>(rb[v]);
+  };
+
+  d4 accd[4][4];
+  f4 accf[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      accd[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accf[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  const int nslab = (K + KS - 1) / KS;
+  load_slab(0);
+  store_slab(0);
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  for (int sl = 0; sl < nslab; ++sl) {
+    const int cur = sl & 1;
+    if (sl + 1 < nslab) load_slab((sl + 1) * KS);
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int kq = 0; kq < KS / 4; ++kq) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = As[cur][kq * 4 + lk][wm * 64 + i * 16 + li];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = Bs[cur][kq * 4 + lk][wn * 64 + j * 16 + li];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            accd[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], accd[i][j], 0, 0, 0);
+      }
+    } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int kq = 0; kq < KS / 4; ++kq) {
+        float av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = As[cur][kq * 4 + lk][wm * 64 + i * 16 + li];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = Bs[cur][kq * 4 + lk][wn * 64 + j * 16 + li];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            accf[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], accf[i][j], 0, 0, 0);
+      }
+    } else {
+      // bf16: one 16x16x32 MFMA per 32-deep slab; lane holds 8 consecutive k
+      s8 av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          av[i][t] = (short)As[cur][lk * 8 + t][wm * 64 + i * 16 + li];
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          bv[j][t] = (short)Bs[cur][lk * 8 + t][wn * 64 + j * 16 + li];
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          accf[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], accf[i][j], 0, 0, 0);
+    }
+    if (sl + 1 < nslab) {
+      store_slab(cur ^ 1);
+    }
+    __syncthreads();
+  }
+
+  // epilogue
+  double amax = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wm * 64 + i * 16 + ((sizeof(T) == 8) ? (lk + 4 * v) : (4 * lk + v));
+        const int c = n0 + wn * 64 + j * 16 + li;
+        if (r < M && c < N) {
+          const double p = (sizeof(T) == 8) ? accd[i][j][v] : (double)accf[i][j][v];
+          double* cp = g.C + (int64_t)r * g.ldc + c;
+          const double val = (g.beta != 0.0) ? fma(g.alpha, p, g.beta * *cp) : g.alpha * p;
+          *cp = val;
+          amax = fmax(amax, fabs(val));
+        }
+      }
+  if (g.amax) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+    if (lane == 0) red[wave] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      atomic_max_pos(g.amax, mx);
+      if (g.amax2) atomic_max_pos(g.amax2, mx);
+    }
+  }
+}
+
+hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream) {
+  if (a.M <= 0 || a.N <= 0) return hipSuccess;
+  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
+  if (a.prec == PRRP_SCHUR_FP32)
+    hipLaunchKernelGGL(gemm_kernel<float>, grid, dim3(kGemmThreads), 0, stream, a);
+  else if (a.prec == PRRP_SCHUR_BF16)
+    hipLaunchKernelGGL(gemm_kernel<unsigned short>, grid, dim3(kGemmThreads), 0, stream, a);
+  else
+    hipLaunchKernelGGL(gemm_kernel<double>, grid, dim3(kGemmThreads), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace prrp

@@ -1,0 +1,117 @@
+// Launch interfaces of the gfx950 kernels (host side of the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "prrp.h"
+
+namespace prrp {
+
+constexpr int kPostW = 2 + 128;   // words per posted candidate: key, slot, row
+constexpr int kMaxGroups = 256;   // tiles per srrqr launch
+
+// ------------------------------------------------------------ strong RRQR
+struct SrrqrArgs {
+  const double* A;
+  int64_t lda;
+  int64_t k0;                 // panel = A[k0 + r, k0 + c], c < bw
+  int bw;
+  int ngroups;                // independent tiles in this launch
+  int G;                      // workgroups per tile
+  int rpw;                    // tile rows per workgroup
+  int32_t tile_start[kMaxGroups];  // first panel row, or offset into row_list
+  int32_t tile_len[kMaxGroups];
+  const int32_t* row_list;    // nullable: tile rows are row_list[tile_start + t]
+  int mode;                   // 0 strong RRQR, 1 given pivots (sel_in), emits M only
+  const int32_t* sel_in;      // mode 1: tile positions in pivot order
+  uint64_t tau_bits;          // truncated encoding of tau
+  int report_rank;            // write rank deficiency into stats->info
+  int record_block_L;         // record max |M| into stats->max_block_L
+  int32_t* sel_out;           // [ngroups][kMaxB] selected panel rows, slot order
+  double* Y;                  // nullable: M^T rows of unselected panel rows
+  int64_t ldy;
+  uint64_t* slots;            // this launch's slot set
+  size_t group_stride;        // words between groups' slot areas
+  int32_t* rounds_out;        // [ngroups] rounds used (for the next launch's clear)
+  uint64_t* clear_base;       // slot set of the previous launch (nullable)
+  size_t clear_group_stride;
+  int clear_ngroups, clear_G, clear_bw;
+  const int32_t* clear_rounds;
+  prrp_stats* stats;
+  uint32_t* abort_flag;
+};
+hipError_t launch_srrqr(const SrrqrArgs& a, hipStream_t stream);
+size_t srrqr_smem_bytes(int bw);
+int srrqr_max_rpw();
+hipError_t srrqr_prepare();   // raise the dynamic LDS limit of every instance
+
+// ----------------------------------------------- diagonal block and moves
+struct GeppArgs {
+  double* A;
+  int64_t lda;
+  int64_t k0;
+  int bw;
+  int m;                      // panel rows
+  const int32_t* sel;         // [bw] selected panel rows in slot order
+  double* PL;                 // [bw][bw]  Pi11 L11 (row p11[j] = row j of L11)
+  double* Linv;               // [bw][bw]  L11^-1
+  int32_t* mv_dst;            // [2 kMaxB] row moves: panel position <- panel row
+  int32_t* mv_src;
+  int32_t* n_moves;
+  prrp_stats* stats;
+};
+hipError_t launch_gepp(const GeppArgs& a, hipStream_t stream);
+
+struct MoveArgs {
+  double* A;
+  int64_t lda;
+  int64_t n;
+  int64_t k0;
+  int bw;
+  const int32_t* mv_dst;
+  const int32_t* mv_src;
+  const int32_t* n_moves;
+  int64_t* perm;
+  double* Y;                  // rows of Y follow displaced rows (nullable)
+  int64_t ldy;
+};
+hipError_t launch_moves(const MoveArgs& a, hipStream_t stream);
+
+// -------------------------------------------------------------- GEMMs
+// C = alpha * A * B + beta * C, row-major, FP64 operands; the Schur variants
+// round A and B to `prec` and accumulate in FP32 (prec != PRRP_FP64).
+// amax (nullable): max |C_new| recorded into *amax.
+struct GemmArgs {
+  int M, N, K;
+  const double* A; int64_t lda;
+  const double* B; int64_t ldb;
+  double* C; int64_t ldc;
+  double alpha, beta;
+  double* amax;               // nullable: max |C_new| recorded here
+  double* amax2;              // nullable: and here
+  int prec;
+};
+hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream);
+
+// -------------------------------------------------------------- misc
+hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
+hipError_t launch_init_factor(const double* A, int64_t n, int64_t lda, int64_t* perm,
+                              prrp_stats* stats, uint32_t* abort_flag, hipStream_t s);
+
+// -------------------------------------------------------------- solves
+hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm, double* X,
+                              int64_t ldx, int64_t n, int64_t nrhs, hipStream_t s);
+hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, double* X, int64_t ldx,
+                               int64_t nrhs, int lower, uint64_t* flags, uint32_t* ticket,
+                               uint32_t epoch, hipStream_t s);
+hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double* X, int64_t ldx,
+                           const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
+                           hipStream_t s);
+hipError_t launch_axpy_maxrel(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t n,
+                              int64_t nrhs, double* out2, hipStream_t s);
+hipError_t launch_build_lists(const int32_t* child_sel, int nchild, int bw, int32_t* lists,
+                              int32_t* promoted_out, int npairs, int flat_tile_start,
+                              int flat_tile_len, hipStream_t s);
+
+}  // namespace prrp

@@ -1,0 +1,116 @@
+// Small helper kernels: fills, factorization start-up (identity permutation,
+// stats record, max |A| for the growth factor's denominator).
+#include "common.h"
+#include "kernels.h"
+
+namespace prrp {
+
+__global__ void fill_u64_kernel(uint64_t* p, size_t n, uint64_t v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+__global__ void init_stats_kernel(prrp_stats* st, uint32_t* abort_flag) {
+  if (threadIdx.x == 0) {
+    st->max_abs_A = 0.0;
+    st->max_abs_W = 0.0;
+    st->max_abs_U = 0.0;
+    st->max_block_L = 0.0;
+    st->swaps = 0;
+    st->info = 0;
+    st->tree_height = 0;
+    st->panels = 0;
+    *abort_flag = 0u;
+  }
+}
+
+// perm = identity; max |A| into max_abs_A and max_abs_W (nonfinite -> info -1)
+__global__ __launch_bounds__(256) void init_factor_kernel(const double* A, int64_t n, int64_t lda,
+                                                          int64_t* perm, prrp_stats* st) {
+  double m = 0.0;
+  bool bad = false;
+  const int64_t total = n * n;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / n, j = e - i * n;
+    const double v = fabs(A[i * lda + j]);
+    if (!(v <= 1.7976931348623157e308)) bad = true;
+    else m = fmax(m, v);
+  }
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) perm[i] = i;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_pos(&st->max_abs_A, m);
+    atomic_max_pos(&st->max_abs_W, m);
+  }
+  if (bad) set_info(st, -1);
+}
+
+hipError_t launch_init_factor(const double* A, int64_t n, int64_t lda, int64_t* perm,
+                              prrp_stats* stats, uint32_t* abort_flag, hipStream_t s) {
+  hipLaunchKernelGGL(init_stats_kernel, dim3(1), dim3(64), 0, s, stats, abort_flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t blocks = (n * n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(init_factor_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, perm,
+                     stats);
+  return hipGetLastError();
+}
+
+// Candidate lists of a tournament level.  Binary tree (flat_tile_start < 0):
+// pair p stacks child 2p's candidates over child 2p+1's, each in increasing
+// row order; an odd last child is copied to promoted_out[npairs].  Flat tree:
+// the running candidates (increasing) over the rows of the next tile.
+__global__ __launch_bounds__(256) void build_lists_kernel(const int32_t* child, int nchild, int bw,
+                                                          int32_t* lists, int32_t* promoted_out,
+                                                          int npairs, int flat_start, int flat_len) {
+  __shared__ int32_t v[2 * kMaxB];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (flat_start >= 0) {
+    if (tid < bw) v[tid] = child[tid];
+    __syncthreads();
+    if (tid < bw) {
+      const int32_t x = v[tid];
+      int rank = 0;
+      for (int j = 0; j < bw; ++j) rank += v[j] < x;
+      lists[rank] = x;
+    }
+    for (int t = tid; t < flat_len; t += 256) lists[bw + t] = flat_start + t;
+    return;
+  }
+  if (p < npairs) {
+    if (tid < 2 * bw) v[tid] = child[(2 * p + tid / bw) * kMaxB + tid % bw];
+    __syncthreads();
+    if (tid < 2 * bw) {
+      const int half = tid / bw;
+      const int32_t x = v[tid];
+      int rank = 0;
+      for (int j = 0; j < bw; ++j) rank += v[half * bw + j] < x;
+      lists[p * 2 * bw + half * bw + rank] = x;
+    }
+  } else if ((nchild & 1) && tid < bw) {
+    promoted_out[npairs * kMaxB + tid] = child[(nchild - 1) * kMaxB + tid];
+  }
+}
+
+hipError_t launch_build_lists(const int32_t* child_sel, int nchild, int bw, int32_t* lists,
+                              int32_t* promoted_out, int npairs, int flat_tile_start,
+                              int flat_tile_len, hipStream_t s) {
+  const int blocks = (flat_tile_start >= 0) ? 1 : npairs + (nchild & 1);
+  hipLaunchKernelGGL(build_lists_kernel, dim3(blocks), dim3(256), 0, s, child_sel, nchild, bw,
+                     lists, promoted_out, npairs, flat_tile_start, flat_tile_len);
+  return hipGetLastError();
+}
+
+}  // namespace prrp

@@ -1,0 +1,252 @@
+// Solves with the in-place factors of A[perm] = L U, the extended-precision
+// residual of iterative refinement, and the refinement update.
+//
+// trsv_kernel: blocked triangular solve with many right-hand sides in one
+// launch.  Workgroups take 64-row blocks in dependency order from a ticket
+// counter; a block accumulates the products with already solved blocks as
+// their completion flags appear (release/acquire through device-scope
+// fences), then solves its diagonal block in one wave per right-hand side.
+//
+// residual_kernel: r = b - A x with the error-free transformations TwoProduct
+// (by FMA) and TwoSum, accumulated per lane as in Ogita, Rump and Oishi's Dot2
+// and combined across the wave by error-free pairwise sums, rounded once.
+#include "common.h"
+#include "kernels.h"
+
+namespace prrp {
+
+namespace {
+constexpr int NB = 64;
+constexpr int RC = 8;    // right-hand sides per pass
+}
+
+__global__ void gather_rows_kernel(const double* B, int64_t ldb, const int64_t* perm, double* X,
+                                   int64_t ldx, int64_t n, int64_t nrhs) {
+  const int64_t total = n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / nrhs, r = e - i * nrhs;
+    X[i * ldx + r] = B[perm[i] * ldb + r];
+  }
+}
+
+hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm, double* X,
+                              int64_t ldx, int64_t n, int64_t nrhs, hipStream_t s) {
+  int64_t blocks = (n * nrhs + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, B, ldb, perm, X,
+                     ldx, n, nrhs);
+  return hipGetLastError();
+}
+
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, int64_t lda,
+                                                   double* X, int64_t ldx, int64_t nrhs,
+                                                   uint64_t* flags, uint32_t* ticket,
+                                                   uint32_t epoch) {
+  __shared__ double D[NB][NB + 1];
+  __shared__ double yj[NB][RC];
+  __shared__ double part[4][NB][RC];
+  __shared__ int blk_s;
+  __shared__ int bad_s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    blk_s = (int)atomicAdd(ticket, 1u);
+    bad_s = 0;
+  }
+  __syncthreads();
+  const int nb = (int)((n + NB - 1) / NB);
+  const int t = blk_s;
+  if (t >= nb) return;
+  const int k = LOWER ? t : nb - 1 - t;
+  const int64_t r0 = (int64_t)k * NB;
+  const int rows = (int)min<int64_t>(NB, n - r0);
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, c = e % NB;
+    D[i][c] = (i < rows && c < rows) ? LU[(r0 + i) * lda + r0 + c] : 0.0;
+  }
+  const int ri = tid & 63, q = tid >> 6;      // row, column quarter
+  for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RC) {
+    const int nr = (int)min<int64_t>(RC, nrhs - rc0);
+    double acc[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[r] = 0.0;
+    const int jb = LOWER ? 0 : k + 1;
+    const int je = LOWER ? k : nb;
+    for (int j = jb; j < je; ++j) {
+      if (tid == 0) {
+        unsigned it = 0;
+        while (ld_dev(&flags[j]) != (uint64_t)epoch) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++it > kSpinLimit) { bad_s = 1; break; }
+        }
+        __threadfence();
+      }
+      __syncthreads();
+      if (bad_s) return;
+      const int64_t c0 = (int64_t)j * NB;
+      const int cols = (int)min<int64_t>(NB, n - c0);
+      for (int e = tid; e < NB * RC; e += 256) {
+        const int c = e / RC, r = e % RC;
+        yj[c][r] = (c < cols && r < nr) ? X[(c0 + c) * ldx + rc0 + r] : 0.0;
+      }
+      __syncthreads();
+      if (ri < rows) {
+        const double* lrow = LU + (r0 + ri) * lda + c0;
+#pragma unroll 4
+        for (int c = q * 16; c < q * 16 + 16; ++c) {
+          if (c < cols) {
+            const double l = lrow[c];
+#pragma unroll
+            for (int r = 0; r < RC; ++r) acc[r] = fma(l, yj[c][r], acc[r]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r) part[q][ri][r] = acc[r];
+    __syncthreads();
+    // one wave per right-hand side solves the diagonal block
+    for (int r = wave; r < nr; r += 4) {
+      double b = 0.0;
+      if (lane < rows)
+        b = X[(r0 + lane) * ldx + rc0 + r] -
+            (part[0][lane][r] + part[1][lane][r] + part[2][lane][r] + part[3][lane][r]);
+      if (LOWER) {
+        for (int i = 0; i < rows; ++i) {
+          const double y = __shfl(b, i, 64);
+          if (lane > i) b = fma(-D[lane][i], y, b);
+        }
+      } else {
+        for (int i = rows - 1; i >= 0; --i) {
+          const double bi = __shfl(b, i, 64);
+          const double y = bi / D[i][i];
+          if (lane == i) b = y;
+          if (lane < i) b = fma(-D[lane][i], y, b);
+        }
+      }
+      if (lane < rows) X[(r0 + lane) * ldx + rc0 + r] = b;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    __threadfence();
+    st_dev(&flags[k], (uint64_t)epoch);
+  }
+}
+
+hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, double* X, int64_t ldx,
+                               int64_t nrhs, int lower, uint64_t* flags, uint32_t* ticket,
+                               uint32_t epoch, hipStream_t s) {
+  const int nb = (int)((n + NB - 1) / NB);
+  if (lower)
+    hipLaunchKernelGGL(trsv_kernel<true>, dim3(nb), dim3(256), 0, s, LU, n, lda, X, ldx, nrhs,
+                       flags, ticket, epoch);
+  else
+    hipLaunchKernelGGL(trsv_kernel<false>, dim3(nb), dim3(256), 0, s, LU, n, lda, X, ldx, nrhs,
+                       flags, ticket, epoch);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ residual
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__global__ __launch_bounds__(256) void residual_kernel(const double* A, int64_t n, int64_t lda,
+                                                       const double* X, int64_t ldx, const double* B,
+                                                       int64_t ldb, double* R, int64_t ldr,
+                                                       int64_t nrhs) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double* arow = A + row * lda;
+  for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RC) {
+    const int nr = (int)min<int64_t>(RC, nrhs - rc0);
+    double p[RC], s[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      p[r] = (lane == 0 && r < nr) ? B[row * ldb + rc0 + r] : 0.0;
+      s[r] = 0.0;
+    }
+    for (int64_t c = lane; c < n; c += 64) {
+      const double a = arow[c];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        if (r < nr) {
+          const double x = X[c * ldx + rc0 + r];
+          const double h = a * x;
+          const double e = fma(a, x, -h);
+          double t, q;
+          two_sum(p[r], -h, t, q);
+          p[r] = t;
+          s[r] += q - e;
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        const double po = __shfl_xor(p[r], o, 64);
+        const double so = __shfl_xor(s[r], o, 64);
+        double t, q;
+        two_sum(p[r], po, t, q);
+        p[r] = t;
+        s[r] = s[r] + so + q;
+      }
+    }
+    if (lane == 0) {
+      for (int r = 0; r < nr; ++r) R[row * ldr + rc0 + r] = p[r] + s[r];
+    }
+  }
+}
+
+hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double* X, int64_t ldx,
+                           const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
+                           hipStream_t s) {
+  const int64_t blocks = (n + 3) / 4;
+  hipLaunchKernelGGL(residual_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, X, ldx,
+                     B, ldb, R, ldr, nrhs);
+  return hipGetLastError();
+}
+
+// X += D; out[2r] = max|D(:,r)|, out[2r+1] = max|X(:,r)| (out zeroed by the caller).
+// One thread per row; maxima reduced per wave before the device-scope max.
+__global__ __launch_bounds__(256) void axpy_maxrel_kernel(double* X, int64_t ldx, const double* D,
+                                                          int64_t ldd, int64_t n, int64_t nrhs,
+                                                          double* out) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  for (int64_t r = 0; r < nrhs; ++r) {
+    double dm = 0.0, xm = 0.0;
+    if (i < n) {
+      const double d = D[i * ldd + r];
+      const double x = X[i * ldx + r] + d;
+      X[i * ldx + r] = x;
+      dm = fabs(d);
+      xm = fabs(x);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      dm = fmax(dm, __shfl_xor(dm, o, 64));
+      xm = fmax(xm, __shfl_xor(xm, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomic_max_pos(&out[2 * r], dm);
+      atomic_max_pos(&out[2 * r + 1], xm);
+    }
+  }
+}
+
+hipError_t launch_axpy_maxrel(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t n,
+                              int64_t nrhs, double* out, hipStream_t s) {
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(axpy_maxrel_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, ldx, D, ldd,
+                     n, nrhs, out);
+  return hipGetLastError();
+}
+
+}  // namespace prrp

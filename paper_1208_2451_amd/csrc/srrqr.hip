@@ -1,0 +1,574 @@
+// Strong rank revealing QR of a panel's transpose on gfx950.
+//
+// Appendix A ("Strong RRQR"): Householder QR with column pivoting of P^T,
+// then interchanges while some |(R11^-1 R12)_ij| > tau.  The columns of P^T
+// are the panel's rows, so a "column" here is a row of the panel.
+//
+// One launch handles `ngroups` independent tiles (a whole LU_PRRP panel, or the
+// leaves / nodes of a CALU_PRRP tournament).  Each tile is owned by G
+// workgroups; every workgroup keeps its share of the tile's rows in registers
+// (8 lanes per row, lane l8 holds columns l8, l8+8, ...).  Each step of the
+// pivoting needs the tile-wide winner: every workgroup posts its best
+// candidate (tie key + the candidate row) into a fresh slot of device memory
+// and reads the G posted keys back; slots start out holding a sentinel and
+// are written exactly once, so readers simply poll until the sentinel is gone
+// (device-scope atomics, no fences).  Slots alternate between two sets from
+// launch to launch; a launch restores the sentinels of the set the previous
+// launch used.
+//
+// Selection rule: QRCP recomputes the squared norm of every candidate's
+// trailing part after each reflection and takes the largest under the tie
+// rule (lowest tile position among equal truncated keys).  After QRCP,
+// M = R11^-1 R12 is formed for every unselected row; while the largest |M|
+// (tie: lowest row, then lowest slot) exceeds tau the row takes that slot and
+// M is updated by the rank-one exchange formula.
+//
+// Mode 1 (CALU_PRRP after the tournament) runs the same Householder steps with
+// given pivots -- the QR without pivoting of the panel transpose with the
+// winners first (Section 3.1) -- and only emits M.
+#include "common.h"
+#include "kernels.h"
+
+namespace prrp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRowGroups = kThreads / 8;
+
+__device__ __forceinline__ double rd8(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  return v;
+}
+__device__ __forceinline__ uint64_t max8(uint64_t v) {
+  uint64_t w;
+  w = __shfl_xor(v, 1, 64); v = w > v ? w : v;
+  w = __shfl_xor(v, 2, 64); v = w > v ? w : v;
+  w = __shfl_xor(v, 4, 64); v = w > v ? w : v;
+  return v;
+}
+
+// Poll a posted word until the sentinel is replaced; bounded.
+__device__ __forceinline__ uint64_t poll_word(const uint64_t* p, const uint32_t* abort_flag,
+                                              int* bad) {
+  uint64_t v = ld_dev(p);
+  unsigned it = 0;
+  while (v == kKeySent) {
+    __builtin_amdgcn_s_sleep(1);
+    v = ld_dev(p);
+    ++it;
+    if ((it & 255u) == 0u && ld_dev_u32(abort_flag) != 0u) { *bad = 1; break; }
+    if (it > kSpinLimit) { *bad = 1; break; }
+  }
+  return v;
+}
+
+struct Smem {
+  double* R;       // R11 packed by columns: R(i,j), i <= j, at j(j+1)/2 + i
+  double* vsh;     // [kMaxB] reflector / exchange vector
+  double* prow;    // [kMaxB] winner's row
+  double* rdiag;   // [kMaxB] 1 / R(i,i)
+  double* scal;    // [8]   beta, gamma, ...
+  uint64_t* red;   // [16]  reduction scratch
+  int* selpos;     // [kMaxB] tile positions in slot order
+  int* flags;      // [8]   0: abort, 1: rank deficient, 2: winner slot
+};
+
+}  // namespace
+
+size_t srrqr_smem_bytes(int bw) {
+  return sizeof(double) * (size_t)(bw * (bw + 1) / 2 + 3 * kMaxB + 8) + sizeof(uint64_t) * 16 +
+         sizeof(int) * (kMaxB + 8);
+}
+
+template <int CPT, int RPT>
+__global__ __launch_bounds__(kThreads) void srrqr_kernel(SrrqrArgs a) {
+  extern __shared__ double smem_raw[];
+  const int bw = a.bw;
+  Smem S;
+  S.R = smem_raw;
+  S.vsh = S.R + bw * (bw + 1) / 2;
+  S.prow = S.vsh + kMaxB;
+  S.rdiag = S.prow + kMaxB;
+  S.scal = S.rdiag + kMaxB;
+  S.red = reinterpret_cast<uint64_t*>(S.scal + 8);
+  S.selpos = reinterpret_cast<int*>(S.red + 16);
+  S.flags = S.selpos + kMaxB;
+
+  const int G = a.G;
+  const int g = blockIdx.x / G;
+  const int w = blockIdx.x - g * G;
+  const int tid = threadIdx.x;
+  const int l8 = tid & 7;
+  const int rg = tid >> 3;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int tlen = a.tile_len[g];
+  const int tstart = a.tile_start[g];
+  const int row0 = w * a.rpw;
+  const int nloc = max(0, min(a.rpw, tlen - row0));
+  uint64_t* slots = a.slots + (size_t)g * a.group_stride;
+  const size_t round_stride = (size_t)G * kPostW;
+
+  // ---- restore the sentinels of the slot set used by the previous launch
+  if (a.clear_base != nullptr) {
+    const int nthr = gridDim.x * kThreads;
+    const int gt = blockIdx.x * kThreads + tid;
+    const int per_post = 2 + a.clear_bw;
+    for (int cg = 0; cg < a.clear_ngroups; ++cg) {
+      const int used = a.clear_rounds[cg];
+      uint64_t* base = a.clear_base + (size_t)cg * a.clear_group_stride;
+      const size_t total = (size_t)used * a.clear_G * per_post;
+      for (size_t e = gt; e < total; e += nthr) {
+        const size_t post = e / per_post;
+        const int wd = (int)(e - post * per_post);
+        base[post * kPostW + wd] = kKeySent;
+      }
+    }
+  }
+
+  // ---- load this workgroup's rows
+  double x[RPT][CPT];
+  int tpos[RPT];
+  bool live[RPT], chosen[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int lr = rg + kRowGroups * q;
+    tpos[q] = row0 + lr;
+    live[q] = lr < nloc;
+    chosen[q] = false;
+    int64_t prow_idx = 0;
+    if (live[q]) prow_idx = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + tpos[q];
+    const double* src = a.A + (a.k0 + prow_idx) * a.lda + a.k0;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int c = l8 + 8 * k;
+      x[q][k] = (live[q] && c < bw) ? src[c] : 0.0;
+    }
+  }
+  if (tid < kMaxB) { S.vsh[tid] = 0.0; }
+  if (tid < 8) S.flags[tid] = 0;
+  __syncthreads();
+
+  int bad = 0;
+  const bool multi = G > 1;
+
+  // ================================================================ QR steps
+  for (int s = 0; s <= bw; ++s) {
+    // (a) apply reflector H_{s-1} to the unselected rows
+    if (s > 0) {
+      const double beta = S.scal[0];
+      double vr[CPT];
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) vr[k] = (l8 + 8 * k < bw) ? S.vsh[l8 + 8 * k] : 0.0;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        if (live[q] && !chosen[q]) {
+          double d = 0.0;
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) d = fma(vr[k], x[q][k], d);
+          d = rd8(d);
+          const double f = beta * d;
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) x[q][k] = fma(-f, vr[k], x[q][k]);
+        }
+      }
+    }
+    if (s == bw) break;
+
+    // (b) pick this step's pivot
+    int p;              // tile position of the pivot
+    if (a.mode == 0) {
+      uint64_t best = 0;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        double nu = 0.0;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          const int c = l8 + 8 * k;
+          nu += (c >= s && c < bw) ? x[q][k] * x[q][k] : 0.0;
+        }
+        nu = rd8(nu);
+        const uint64_t key = (live[q] && !chosen[q]) ? make_key(nu, (uint32_t)tpos[q]) : 0ull;
+        best = key > best ? key : best;
+      }
+      best = wave_max_u64(best);
+      if (lane == 0) S.red[wave] = best;
+      __syncthreads();
+      uint64_t wkey = S.red[0];
+#pragma unroll
+      for (int i = 1; i < kThreads / 64; ++i) wkey = S.red[i] > wkey ? S.red[i] : wkey;
+      uint64_t gkey = wkey;
+      uint64_t* post_r = slots + (size_t)s * round_stride;
+      if (multi) {
+        // post my candidate (key + row); the owner's 8 lanes write the row
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          if (wkey != 0 && live[q] && !chosen[q] && (uint32_t)tpos[q] == key_index(wkey)) {
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+              const int c = l8 + 8 * k;
+              if (c < bw)
+                st_dev(post_r + (size_t)w * kPostW + 2 + c,
+                       (uint64_t)__double_as_longlong(x[q][k]));
+            }
+          }
+        }
+        if (tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
+        __syncthreads();   // S.red reuse below
+        uint64_t kv = 0;
+        if (tid < G) kv = poll_word(post_r + (size_t)tid * kPostW, a.abort_flag, &bad);
+        kv = wave_max_u64(kv);
+        if (lane == 0) S.red[4 + wave] = kv;
+        if (bad) S.flags[0] = 1;
+        __syncthreads();
+        gkey = S.red[4];
+#pragma unroll
+        for (int i = 1; i < kThreads / 64; ++i) gkey = S.red[4 + i] > gkey ? S.red[4 + i] : gkey;
+        if (S.flags[0]) break;
+      }
+      if (gkey == 0) {       // fewer rows than columns: cannot happen for valid tiles
+        if (tid == 0) set_info(a.stats, -2);
+        break;
+      }
+      if (key_nonfinite(gkey) && tid == 0) set_info(a.stats, -1);
+      if ((gkey >> kDropBits) == 0) {   // exactly zero residual: rank deficient
+        if (tid == 0) {
+          S.flags[1] = 1;
+          if (a.report_rank) set_info(a.stats, (int32_t)(a.k0 + s + 1));
+        }
+      }
+      p = (int)key_index(gkey);
+    } else {
+      p = a.sel_in[s];
+    }
+
+    // (c) bring the pivot row into LDS
+    const int owner = p / a.rpw;
+    uint64_t* post_r = slots + (size_t)s * round_stride;
+    if (owner == w) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        if (live[q] && tpos[q] == p) {
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) {
+            const int c = l8 + 8 * k;
+            if (c < bw) {
+              S.prow[c] = x[q][k];
+              if (a.mode == 1 && multi)
+                st_dev(post_r + (size_t)w * kPostW + 2 + c, (uint64_t)__double_as_longlong(x[q][k]));
+            }
+          }
+          chosen[q] = true;
+        }
+      }
+    } else {
+      if (tid < bw) {
+        const uint64_t v = poll_word(post_r + (size_t)owner * kPostW + 2 + tid, a.abort_flag, &bad);
+        S.prow[tid] = __longlong_as_double((long long)v);
+      }
+      if (bad) S.flags[0] = 1;
+    }
+    if (tid == 0) S.selpos[s] = p;
+    __syncthreads();
+    if (S.flags[0]) break;
+
+    // (d) reflector from prow[s:bw); R column s
+    if (wave == 0) {
+      const int c0 = s + lane, c1 = s + lane + 64;
+      const double x0 = (c0 < bw) ? S.prow[c0] : 0.0;
+      const double x1 = (c1 < bw) ? S.prow[c1] : 0.0;
+      const double tail = wave_sum((lane == 0 ? 0.0 : x0 * x0) + x1 * x1);  // sum over c > s
+      const double head = S.prow[s];
+      const double nrm = sqrt(fma(head, head, tail));
+      const double alpha = (nrm == 0.0) ? 0.0 : -copysign(nrm, head);
+      const double v0 = head - alpha;
+      const double vtv = fma(v0, v0, tail);
+      if (c0 < bw) S.vsh[c0] = (lane == 0) ? v0 : x0;
+      if (c1 < bw) S.vsh[c1] = x1;
+      if (lane == 0) {
+        S.scal[0] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+        S.R[s * (s + 1) / 2 + s] = alpha;
+      }
+      if (lane < s && lane < bw) S.vsh[lane] = 0.0;
+      if (lane + 64 < s && lane + 64 < bw) S.vsh[lane + 64] = 0.0;
+    } else if (wave == 1) {
+      for (int i = lane; i < s; i += 64) S.R[s * (s + 1) / 2 + i] = S.prow[i];
+    }
+    __syncthreads();
+  }
+
+  if (S.flags[0]) {
+    if (tid == 0) {
+      set_info(a.stats, -2);
+      st_dev_u32(a.abort_flag, 1u);
+    }
+    return;
+  }
+
+  int rounds_used = bw;
+  int swaps = 0;
+  const bool rank_def = S.flags[1] != 0;
+  const bool need_m = (a.mode == 1) ? (a.Y != nullptr) : true;
+  double mmax_local = 0.0;
+
+  if (need_m && !rank_def && tlen > bw) {
+    // ============================================= M = R11^-1 R12 per row
+    if (tid < bw) S.rdiag[tid] = 1.0 / S.R[tid * (tid + 1) / 2 + tid];
+    __syncthreads();
+#pragma unroll
+    for (int kk = CPT - 1; kk >= 0; --kk) {
+#pragma unroll
+      for (int li = 7; li >= 0; --li) {
+        const int i = 8 * kk + li;
+        if (i >= bw) continue;
+        double rcol[CPT];
+#pragma unroll
+        for (int k = 0; k <= kk; ++k) {
+          const int c = l8 + 8 * k;
+          rcol[k] = (c < i) ? S.R[i * (i + 1) / 2 + c] : 0.0;
+        }
+        const double di = S.rdiag[i];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const double yi = __shfl(x[q][kk], (lane & ~7) | li, 64) * di;
+          if (l8 == li) x[q][kk] = yi;
+#pragma unroll
+          for (int k = 0; k <= kk; ++k) x[q][k] = fma(-rcol[k], yi, x[q][k]);
+        }
+      }
+    }
+    // x[q] now holds column M(:, row) for unselected rows (garbage for chosen)
+
+    if (a.mode == 0) {
+      // ========================================== exchange loop (Appendix A)
+      if (tid < bw) S.vsh[tid] = 0.0;
+      for (int e = 0;; ++e) {
+        const int r = bw + e;
+        // best (magnitude, slot) per row, then best row
+        uint64_t best = 0;
+        int best_slot = 0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          uint64_t sk = 0;
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) {
+            const int c = l8 + 8 * k;
+            if (c < bw) {
+              const uint64_t kk2 = make_key(fabs(x[q][k]), (uint32_t)c);
+              sk = kk2 > sk ? kk2 : sk;
+            }
+          }
+          sk = max8(sk);
+          if (live[q] && !chosen[q]) {
+            const uint64_t rk = ((sk >> kDropBits) << kDropBits) | (kIdxMask - (uint32_t)tpos[q]);
+            if (rk > best) { best = rk; best_slot = (int)key_index(sk); }
+          }
+        }
+        const uint64_t wbest = wave_max_u64(best);
+        if (lane == 0) S.red[wave] = wbest;
+        __syncthreads();
+        uint64_t wkey = S.red[0];
+#pragma unroll
+        for (int i = 1; i < kThreads / 64; ++i) wkey = S.red[i] > wkey ? S.red[i] : wkey;
+        // the owner of the workgroup's best records its slot and row
+        const bool own = (best == wkey && wkey != 0);
+        uint64_t* post_r = slots + (size_t)r * round_stride;
+        if (own && l8 == 0) S.flags[2] = best_slot;
+        __syncthreads();
+        const int wslot = S.flags[2];
+        uint64_t gkey = wkey;
+        int gslot = wslot;
+        int gowner = w;
+        if (multi) {
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) {
+            if (wkey != 0 && live[q] && !chosen[q] && (uint32_t)tpos[q] == key_index(wkey)) {
+#pragma unroll
+              for (int k = 0; k < CPT; ++k) {
+                const int c = l8 + 8 * k;
+                if (c < bw)
+                  st_dev(post_r + (size_t)w * kPostW + 2 + c, (uint64_t)__double_as_longlong(x[q][k]));
+              }
+              if (l8 == 0) st_dev(post_r + (size_t)w * kPostW + 1, (uint64_t)wslot);
+            }
+          }
+          if (tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
+          uint64_t kv = 0;
+          if (tid < G) kv = poll_word(post_r + (size_t)tid * kPostW, a.abort_flag, &bad);
+          kv = wave_max_u64(kv);
+          if (lane == 0) S.red[4 + wave] = kv;
+          if (bad) S.flags[0] = 1;
+          __syncthreads();
+          if (S.flags[0]) break;
+          gkey = S.red[4];
+#pragma unroll
+          for (int i = 1; i < kThreads / 64; ++i) gkey = S.red[4 + i] > gkey ? S.red[4 + i] : gkey;
+          gowner = (int)key_index(gkey) / a.rpw;
+        }
+        rounds_used = r + 1;
+        const bool violate = gkey != 0 && (gkey >> kDropBits) > a.tau_bits;
+        if (!violate) break;
+        if (e >= kMaxExchange) {
+          if (tid == 0) set_info(a.stats, -3);
+          break;
+        }
+        const int pj = (int)key_index(gkey);
+        // fetch slot and M column of the incoming row
+        if (gowner == w) {
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) {
+            if (live[q] && tpos[q] == pj) {
+#pragma unroll
+              for (int k = 0; k < CPT; ++k) {
+                const int c = l8 + 8 * k;
+                if (c < bw) S.prow[c] = x[q][k];
+              }
+            }
+          }
+          if (tid == 0) S.flags[3] = wslot;
+        } else {
+          if (tid < bw) {
+            const uint64_t v = poll_word(post_r + (size_t)gowner * kPostW + 2 + tid, a.abort_flag, &bad);
+            S.prow[tid] = __longlong_as_double((long long)v);
+          }
+          if (tid == 64) {
+            const uint64_t v = poll_word(post_r + (size_t)gowner * kPostW + 1, a.abort_flag, &bad);
+            S.flags[3] = (int)v;
+          }
+          if (bad) S.flags[0] = 1;
+        }
+        __syncthreads();
+        if (S.flags[0]) break;
+        gslot = S.flags[3];
+        const int out_pos = S.selpos[gslot];
+        const double gamma = S.prow[gslot];
+        if (tid < bw) S.vsh[tid] = S.prow[tid] - (tid == gslot ? 1.0 : 0.0);   // u = M(:,j) - e_i
+        __syncthreads();
+        if (tid == 0) S.selpos[gslot] = pj;
+        const double ginv = 1.0 / gamma;
+        double ur[CPT];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) ur[k] = (l8 + 8 * k < bw) ? S.vsh[l8 + 8 * k] : 0.0;
+        const int kk_i = gslot >> 3, li_i = gslot & 7;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          double xi = 0.0;
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) xi = (k == kk_i) ? x[q][k] : xi;
+          const double ri = __shfl(xi, (lane & ~7) | li_i, 64);
+          if (!live[q]) continue;
+          if (tpos[q] == pj) {
+            chosen[q] = true;
+          } else if (tpos[q] == out_pos) {
+            chosen[q] = false;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+              const int c = l8 + 8 * k;
+              x[q][k] = ((c == gslot) ? 1.0 : 0.0) - ur[k] * ginv;
+            }
+          } else if (!chosen[q]) {
+            const double f = ri * ginv;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) x[q][k] = fma(-ur[k], f, x[q][k]);
+          }
+        }
+        ++swaps;
+        __syncthreads();
+      }
+      if (S.flags[0]) {
+        if (tid == 0) { set_info(a.stats, -2); st_dev_u32(a.abort_flag, 1u); }
+        return;
+      }
+    }
+
+    // ----------------------------------------------- outputs: Y rows, max|M|
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (live[q] && !chosen[q]) {
+        const int64_t pr = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + tpos[q];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          const int c = l8 + 8 * k;
+          if (c < bw) {
+            mmax_local = fmax(mmax_local, fabs(x[q][k]));
+            if (a.Y) a.Y[pr * a.ldy + c] = x[q][k];
+          }
+        }
+      }
+    }
+  }
+
+  if (rank_def && a.Y) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (live[q] && !chosen[q]) {
+        const int64_t pr = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + tpos[q];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+          if (l8 + 8 * k < bw) a.Y[pr * a.ldy + l8 + 8 * k] = 0.0;
+      }
+    }
+  }
+
+  // ------------------------------------------------------ selection, stats
+  if (w == 0 && tid < bw) {
+    const int sp = S.selpos[tid];
+    a.sel_out[g * kMaxB + tid] = a.row_list ? a.row_list[tstart + sp] : tstart + sp;
+  }
+  if (a.stats) {
+    double m = mmax_local;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0 && m > 0.0 && a.record_block_L) atomic_max_pos(&a.stats->max_block_L, m);
+    if (w == 0 && tid == 0 && swaps > 0)
+      __hip_atomic_fetch_add(&a.stats->swaps, (int64_t)swaps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (w == 0 && tid == 0) a.rounds_out[g] = rounds_used;
+}
+
+// ------------------------------------------------------------- dispatch
+#define PRRP_SRRQR_CASE(C, R)                                                              \
+  if (cpt == C && rpt == R) {                                                              \
+    hipLaunchKernelGGL((srrqr_kernel<C, R>), dim3(a.ngroups * a.G), dim3(kThreads), smem, \
+                       stream, a);                                                         \
+    return hipGetLastError();                                                              \
+  }
+
+hipError_t launch_srrqr(const SrrqrArgs& a, hipStream_t stream) {
+  int cpt = (a.bw + 7) / 8;
+  cpt = cpt <= 2 ? (cpt <= 1 ? 1 : 2) : (cpt <= 4 ? 4 : (cpt <= 8 ? 8 : 16));
+  const int rpt = (a.rpw + kRowGroups - 1) / kRowGroups;
+  const size_t smem = srrqr_smem_bytes(a.bw);
+  PRRP_SRRQR_CASE(1, 1) PRRP_SRRQR_CASE(1, 2) PRRP_SRRQR_CASE(1, 3) PRRP_SRRQR_CASE(1, 4)
+  PRRP_SRRQR_CASE(2, 1) PRRP_SRRQR_CASE(2, 2) PRRP_SRRQR_CASE(2, 3) PRRP_SRRQR_CASE(2, 4)
+  PRRP_SRRQR_CASE(4, 1) PRRP_SRRQR_CASE(4, 2) PRRP_SRRQR_CASE(4, 3) PRRP_SRRQR_CASE(4, 4)
+  PRRP_SRRQR_CASE(8, 1) PRRP_SRRQR_CASE(8, 2) PRRP_SRRQR_CASE(8, 3) PRRP_SRRQR_CASE(8, 4)
+  PRRP_SRRQR_CASE(16, 1) PRRP_SRRQR_CASE(16, 2) PRRP_SRRQR_CASE(16, 3) PRRP_SRRQR_CASE(16, 4)
+  return hipErrorInvalidValue;
+}
+
+int srrqr_max_rpw() { return kRowGroups * 4; }
+
+#define PRRP_SRRQR_ATTR(C, R)                                                               \
+  e = hipFuncSetAttribute((const void*)srrqr_kernel<C, R>,                                  \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);           \
+  if (e != hipSuccess) return e;
+
+hipError_t srrqr_prepare() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  const size_t smem = srrqr_smem_bytes(kMaxB);
+  hipError_t e;
+  PRRP_SRRQR_ATTR(1, 1) PRRP_SRRQR_ATTR(1, 2) PRRP_SRRQR_ATTR(1, 3) PRRP_SRRQR_ATTR(1, 4)
+  PRRP_SRRQR_ATTR(2, 1) PRRP_SRRQR_ATTR(2, 2) PRRP_SRRQR_ATTR(2, 3) PRRP_SRRQR_ATTR(2, 4)
+  PRRP_SRRQR_ATTR(4, 1) PRRP_SRRQR_ATTR(4, 2) PRRP_SRRQR_ATTR(4, 3) PRRP_SRRQR_ATTR(4, 4)
+  PRRP_SRRQR_ATTR(8, 1) PRRP_SRRQR_ATTR(8, 2) PRRP_SRRQR_ATTR(8, 3) PRRP_SRRQR_ATTR(8, 4)
+  PRRP_SRRQR_ATTR(16, 1) PRRP_SRRQR_ATTR(16, 2) PRRP_SRRQR_ATTR(16, 3) PRRP_SRRQR_ATTR(16, 4)
+  done = true;
+  return hipSuccess;
+}
+
+}  // namespace prrp

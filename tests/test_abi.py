@@ -1,0 +1,96 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function the
+header declares, answers workspace queries, and rejects bad arguments before
+touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1208_2451_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "prrp.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(prrp_\w+|calu_prrp_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libprrp.so not built")
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) <= set(_lib._SIGS), "binding misses a declared entry point"
+
+
+def test_version_and_status(L):
+    assert L.prrp_version().decode().startswith("prrp-gfx950")
+    assert L.prrp_status_string(0).decode() == "success"
+
+
+def test_workspace_queries(L):
+    w1 = _lib.workspace_size(256, 16, 0, 0)
+    w2 = _lib.workspace_size(4096, 64, 0, 0)
+    assert 0 < w1 < w2
+    assert _lib.workspace_size(16384, 128, 1, 512) > 0
+    assert _lib.solve_workspace_size(4096, 16) >= 2 * 4096 * 16 * 8
+    with pytest.raises(_lib.PrrpError):
+        _lib.workspace_size(100, 129, 0, 0)         # b above the widest panel
+    with pytest.raises(_lib.PrrpError):
+        _lib.workspace_size(100, 16, 1, 16)         # tile_rows < b + 1
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 8, 8, 2, 2.0), -1),        # null A
+    ((1, 0, 8, 2, 2.0), -2),           # n < 1
+    ((1, 8, 7, 2, 2.0), -3),           # lda < n
+    ((1, 8, 8, 0, 2.0), -4),           # b < 1
+    ((1, 8, 8, 9, 2.0), -4),           # b > n
+    ((1, 8, 8, 2, 1.0), -5),           # tau <= 1
+    ((1, 8, 8, 2, float("nan")), -5),  # tau NaN
+])
+def test_factor_argument_errors(L, args, code):
+    A, n, lda, b, tau = args
+    rc = L.prrp_factor(A, n, lda, b, tau, 1, 1, 1, 1 << 40, None)
+    assert rc == code
+
+
+def test_factor_null_perm_stats_ws(L):
+    assert L.prrp_factor(1, 8, 8, 2, 2.0, None, 1, 1, 1 << 40, None) == -6
+    assert L.prrp_factor(1, 8, 8, 2, 2.0, 1, None, 1, 1 << 40, None) == -7
+    assert L.prrp_factor(1, 8, 8, 2, 2.0, 1, 1, None, 1 << 40, None) == -8
+    assert L.prrp_factor(1, 8, 8, 2, 2.0, 1, 1, 1, 16, None) == -9    # workspace too small
+
+
+def test_calu_argument_errors(L):
+    f = L.calu_prrp_factor
+    assert f(1, 64, 64, 8, 2.0, 2, 32, 1, 1, 1, 1 << 40, None, 0) == -6    # tree kind
+    assert f(1, 64, 64, 8, 2.0, 0, 8, 1, 1, 1, 1 << 40, None, 0) == -7     # tile_rows <= b
+    assert f(1, 64, 64, 8, 2.0, 0, 32, 1, 1, 1, 1 << 40, None, 5) == -13   # precision
+
+
+def test_solve_and_gemm_argument_errors(L):
+    assert L.prrp_solve(None, 8, 8, 1, 1, 1, 1, 1, 1 << 30, None) == -1
+    assert L.prrp_solve(1, 8, 8, 1, 1, 0, 1, 1, 1 << 30, None) == -6
+    assert L.prrp_solve(1, 8, 8, 1, 1, 2, 1, 1, 1 << 30, None) == -7
+    assert L.prrp_residual(1, 8, 4, 1, 1, 1, 1, 1, None) == -3
+    assert L.prrp_gemm(4, 4, 4, 1.0, 1, 3, 1, 4, 0.0, 1, 4, 0, None) == -6
+    assert L.prrp_gemm(4, 4, 4, 1.0, 1, 4, 1, 4, 0.0, 1, 4, 7, None) == -12
+
+
+def test_refine_argument_errors(L):
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0)
+    assert L.prrp_refine(1, 1, 8, 8, 1, 1, 1, 1, 1, -1.0, 5, ctypes.byref(it), ctypes.byref(rel),
+                         1, 1 << 30, None) == -10

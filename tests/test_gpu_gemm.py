@@ -1,0 +1,29 @@
+"""GPU check of the MFMA GEMM (the Schur-update kernel) against an FP64 CPU
+product: FP64 to rounding; FP32 / BF16 operand rounding within their unit
+roundoff bounds.  Odd sizes exercise every tile edge."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-14), ("fp32", 2e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (130, 257, 33), (300, 129, 128), (7, 5, 3)])
+def test_gemm_matches_cpu(prec, tol, M, N, K):
+    import torch
+    import paper_1208_2451_amd as prrp
+    announce("gemm", prec, M, N, K)
+    g = np.random.default_rng(M * 7 + N + K)
+    A = g.standard_normal((M, K))
+    B = g.standard_normal((K, N))
+    C0 = g.standard_normal((M, N))
+    Ct = torch.from_numpy(C0.copy()).cuda()
+    prrp.gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), Ct, alpha=-1.0, beta=1.0,
+              precision=prec)
+    torch.cuda.synchronize()
+    ref = C0 - A @ B
+    err = np.abs(Ct.cpu().numpy() - ref).max()
+    scale = (np.abs(A) @ np.abs(B)).max()
+    assert err <= tol * scale
