@@ -135,6 +135,17 @@ int prrp_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, in
               const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int prec,
               void* stream);
 
+/* Per-phase device timing of factor calls (HIP events around every launch on
+ * the factor's stream).  prrp_profile_enable(1) clears the counters and starts
+ * recording; while enabled each factor call keeps its events until
+ * prrp_profile_read, which waits for them and returns, per phase, the summed
+ * milliseconds and the number of launches (arrays of PRRP_PHASES entries;
+ * either may be NULL).  Phases: 0 strong RRQR / tournament, 1 diagonal GEPP,
+ * 2 row moves, 3 L21 product, 4 U12 product, 5 Schur update, 6 start-up. */
+#define PRRP_PHASES 7
+int prrp_profile_enable(int on);
+int prrp_profile_read(double* ms, int64_t* launches);
+
 /* Human-readable text for a return code or an info value. */
 const char* prrp_status_string(int code);
 

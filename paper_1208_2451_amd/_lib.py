@@ -47,6 +47,8 @@ _SIGS = {
     "prrp_refine": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _dbl, _i32,
                            ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _sz, _vp]),
     "prrp_gemm": (_i32, [_i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64, _dbl, _vp, _i64, _i32, _vp]),
+    "prrp_profile_enable": (_i32, [_i32]),
+    "prrp_profile_read": (_i32, [ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
     "prrp_status_string": (ctypes.c_char_p, [_i32]),
     "prrp_version": (ctypes.c_char_p, []),
 }
@@ -91,3 +93,17 @@ def solve_workspace_size(n: int, nrhs: int) -> int:
     out = ctypes.c_size_t(0)
     check(lib().prrp_solve_workspace_size(n, nrhs, ctypes.byref(out)), "prrp_solve_workspace_size")
     return out.value
+
+
+PHASES = ["srrqr", "gepp", "moves", "l21", "u12", "schur", "startup"]
+
+
+def profile_enable(on: bool = True) -> None:
+    lib().prrp_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    ms = (ctypes.c_double * len(PHASES))()
+    cnt = (ctypes.c_int64 * len(PHASES))()
+    lib().prrp_profile_read(ms, cnt)
+    return {p: (ms[i], cnt[i]) for i, p in enumerate(PHASES)}

@@ -18,6 +18,10 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libprrp.so")
 SOURCES = ["srrqr.hip", "gepp.hip", "gemm.hip", "misc.hip", "solve.hip", "api.cpp"]
+# The strong-RRQR kernel keeps panel rows in registers; its fully unrolled
+# back substitution must stay unrolled (a partial unroll makes register-array
+# indices dynamic and spills them), which needs a higher pragma limit.
+EXTRA = {"srrqr.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
 
 
 def _hipcc() -> str:
@@ -43,7 +47,7 @@ def build(verbose: bool = False) -> str:
 
     def one(src):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + flags() + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [hipcc] + flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -3,9 +3,10 @@
 // prrp_factor runs Algorithm "LU_PRRP factorization" (Section 2.1) one panel
 // at a time on one stream:
 //   srrqr  -- strong RRQR of the panel transpose (pivot rows, M = R11^-1 R12)
-//   gepp   -- transposition plan, GEPP of the b x b block, Pi11 L11, L11^-1
+//   gepp   -- transposition plan, GEPP of the b x b block, Pi11 L11
 //   moves  -- the row interchanges applied to the columns outside the panel
-//   gemm   -- L21 = M^T (Pi11 L11), U12 = L11^-1 A12, A22 -= L21 U12
+//   trsm   -- U12 = L11^-1 A12
+//   gemm   -- L21 = M^T (Pi11 L11), A22 -= L21 U12
 // calu_prrp_factor replaces the srrqr step by a tournament (Section 3.1):
 // strong RRQR of every row tile, then of stacked candidate pairs up a binary
 // tree (or along a chain), and finally the QR with the winners as pivots.
@@ -15,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <vector>
+#include <cstdlib>
 
 #include "common.h"
 #include "kernels.h"
@@ -66,10 +68,25 @@ Tiles tile_bounds(int64_t m, int64_t tile_rows, int b) {
   return t;
 }
 
-// Workgroups per tile so that a tile's rows fit the register budget (at most
-// 128 rows per workgroup) and no workgroup is left without rows.
+// Workgroups per tile.  Each pivot step costs one device-scope round trip
+// whose latency grows with the number of workgroups polled (~1.8 us at 64,
+// ~3.3 us at 256 on MI355X), while fewer workgroups mean more rows each (at
+// most 128, the register budget).  Default: at most 64 rows per workgroup,
+// at most PRRP_PANEL_WGS (default 128) workgroups; none left without rows.
+int panel_wg_cap() {
+  static int cap = 0;
+  if (cap == 0) {
+    const char* e = getenv("PRRP_PANEL_WGS");
+    cap = e ? atoi(e) : 128;
+    if (cap < 1) cap = 1;
+    if (cap > 256) cap = 256;
+  }
+  return cap;
+}
+
 int groups_for_rows(int64_t rows, int cap) {
-  int G = (int)std::min<int64_t>(cap, (rows + 31) / 32);
+  cap = std::min(cap, panel_wg_cap());
+  int G = (int)std::min<int64_t>(cap, (rows + 63) / 64);
   if (G < 1) G = 1;
   while ((rows + G - 1) / G > kRowsPerWgMax) ++G;
   const int64_t rpw = (rows + G - 1) / G;
@@ -117,6 +134,49 @@ Layout make_layout(int64_t n, int b, int method, int64_t tile_rows) {
 }
 
 inline int herr(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
+
+// ------------------------------------------------------------ phase timer
+struct PhaseTimer {
+  bool on = false;
+  struct Rec { int phase; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double ms[PRRP_PHASES] = {0};
+  int64_t count[PRRP_PHASES] = {0};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void drain() {
+    for (auto& r : recs) {
+      float t = 0.f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.phase] += t;
+        count[r.phase] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+};
+PhaseTimer g_timer;
+
+// Scope that brackets one launch with events when the timer is on.
+struct PhaseScope {
+  int phase; hipStream_t st; hipEvent_t a = nullptr, b = nullptr;
+  PhaseScope(int p, hipStream_t s) : phase(p), st(s) {
+    if (g_timer.on) { a = g_timer.get(); if (a) (void)hipEventRecord(a, st); }
+  }
+  ~PhaseScope() {
+    if (g_timer.on && a) {
+      b = g_timer.get();
+      if (b) { (void)hipEventRecord(b, st); g_timer.recs.push_back({phase, a, b}); }
+    }
+  }
+};
 #define PRRP_TRY(x)                                   \
   do {                                                \
     hipError_t e_ = (x);                              \
@@ -172,7 +232,11 @@ struct Ctx {
     a.stats = stats;
     a.abort_flag = abort_flag();
     a.tau_bits = tau_bits(tau);
-    hipError_t e = launch_srrqr(a, st);
+    hipError_t e;
+    {
+      PhaseScope ps(0, st);
+      e = launch_srrqr(a, st);
+    }
     prev_base = a.slots;
     prev_group_stride = a.group_stride;
     prev_ngroups = a.ngroups;
@@ -189,27 +253,41 @@ struct Ctx {
     int32_t* mv_dst = mv();
     int32_t* mv_src = mv() + 2 * kMaxB;
     int32_t* n_moves = mv() + 4 * kMaxB;
-    GeppArgs ga{A, lda, k0, bw, (int)m, sel(), PL(), Linv(), mv_dst, mv_src, n_moves, stats};
-    hipError_t e = launch_gepp(ga, st);
+    GeppArgs ga{A, lda, k0, bw, (int)m, sel(), PL(), mv_dst, mv_src, n_moves, stats};
+    hipError_t e;
+    {
+      PhaseScope ps(1, st);
+      e = launch_gepp(ga, st);
+    }
     if (e != hipSuccess) return e;
     MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, (m > bw) ? Y() : nullptr, b};
-    e = launch_moves(ma, st);
+    {
+      PhaseScope ps(2, st);
+      e = launch_moves(ma, st);
+    }
     if (e != hipSuccess) return e;
     if (m > bw) {
       // L21 = M^T (Pi11 L11)
       GemmArgs l21{(int)(m - bw), bw, bw, Y() + (size_t)bw * b, b, PL(), bw,
                    A + (k0 + bw) * lda + k0, lda, 1.0, 0.0, nullptr, nullptr, PRRP_FP64};
-      e = launch_gemm(l21, st);
+      {
+        PhaseScope ps(3, st);
+        e = launch_gemm(l21, st);
+      }
       if (e != hipSuccess) return e;
       const int64_t nr = n - k0 - bw;
       double* a12 = A + k0 * lda + k0 + bw;
-      GemmArgs u12{bw, (int)nr, bw, Linv(), bw, a12, lda, a12, lda, 1.0, 0.0,
-                   &stats->max_abs_U, &stats->max_abs_W, PRRP_FP64};
-      e = launch_gemm(u12, st);
+      {
+        PhaseScope ps(4, st);
+        e = launch_trsm_u12(A, lda, k0, bw, nr, &stats->max_abs_U, &stats->max_abs_W, st);
+      }
       if (e != hipSuccess) return e;
       GemmArgs sc{(int)(m - bw), (int)nr, bw, A + (k0 + bw) * lda + k0, lda, a12, lda,
                   A + (k0 + bw) * lda + k0 + bw, lda, -1.0, 1.0, &stats->max_abs_W, nullptr, schur};
-      e = launch_gemm(sc, st);
+      {
+        PhaseScope ps(5, st);
+        e = launch_gemm(sc, st);
+      }
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -251,8 +329,11 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
   c.cap = std::min(256, device_cus());
   c.L = make_layout(n, b, method, tile_rows);
   PRRP_TRY(srrqr_prepare());
-  PRRP_TRY(launch_init_factor(A, n, lda, perm, stats, c.abort_flag(), c.st));
-  PRRP_TRY(launch_fill_u64(c.slot_set(0), 2 * c.L.slots_set_words, kKeySent, c.st));
+  {
+    PhaseScope ps(6, c.st);
+    PRRP_TRY(launch_init_factor(A, n, lda, perm, stats, c.abort_flag(), c.st));
+    PRRP_TRY(launch_fill_u64(c.slot_set(0), 2 * c.L.slots_set_words, kKeySent, c.st));
+  }
 
   for (int64_t k0 = 0; k0 < n; k0 += b) {
     const int bw = (int)std::min<int64_t>(b, n - k0);
@@ -359,6 +440,22 @@ extern "C" {
 
 const char* prrp_version(void) { return "prrp-gfx950 0.1"; }
 
+int prrp_profile_enable(int on) {
+  g_timer.drain();
+  for (int p = 0; p < PRRP_PHASES; ++p) { g_timer.ms[p] = 0.0; g_timer.count[p] = 0; }
+  g_timer.on = on != 0;
+  return 0;
+}
+
+int prrp_profile_read(double* ms, int64_t* launches) {
+  g_timer.drain();
+  for (int p = 0; p < PRRP_PHASES; ++p) {
+    if (ms) ms[p] = g_timer.ms[p];
+    if (launches) launches[p] = g_timer.count[p];
+  }
+  return 0;
+}
+
 const char* prrp_status_string(int code) {
   switch (code) {
     case 0: return "success";
@@ -441,28 +538,37 @@ int prrp_solve_workspace_size(int64_t n, int64_t nrhs, size_t* bytes) {
   if (n < 1 || n > kMaxN) return -1;
   if (nrhs < 1) return -2;
   if (!bytes) return -3;
-  const int64_t nb = (n + 63) / 64;
-  // flags + ticket | two n x nrhs vectors (refinement) | 2 nrhs maxima
-  *bytes = align_up((size_t)(nb + 8) * 8, 256) + 2 * align_up((size_t)n * nrhs * 8, 256) +
-           align_up((size_t)nrhs * 16 + 16, 256);
+  // ticket | three n x nrhs vectors (two solve buffers, refinement residual) | maxima
+  *bytes = 256 + 3 * align_up((size_t)n * nrhs * 8, 256) + align_up((size_t)nrhs * 16 + 16, 256);
   return 0;
 }
 
 namespace {
+struct SolveWs {
+  uint32_t* ticket;
+  double *t1, *t2, *r, *mx;
+  SolveWs(char* ws, int64_t n, int64_t nrhs) {
+    const size_t v = align_up((size_t)n * nrhs * 8, 256);
+    ticket = reinterpret_cast<uint32_t*>(ws);
+    t1 = reinterpret_cast<double*>(ws + 256);
+    t2 = reinterpret_cast<double*>(ws + 256 + v);
+    r = reinterpret_cast<double*>(ws + 256 + 2 * v);
+    mx = reinterpret_cast<double*>(ws + 256 + 3 * v);
+  }
+};
+
+// X = U^-1 L^-1 B[perm]; X may alias B.
 int solve_impl(const double* LU, int64_t n, int64_t lda, const int64_t* perm, const double* Bsrc,
                int64_t ldb, double* X, int64_t nrhs, int64_t ldx, char* ws, hipStream_t st) {
-  const int64_t nb = (n + 63) / 64;
-  uint64_t* flags = reinterpret_cast<uint64_t*>(ws);
-  uint32_t* ticket = reinterpret_cast<uint32_t*>(flags + nb);
-  double* tmp = reinterpret_cast<double*>(ws + align_up((size_t)(nb + 8) * 8, 256));
-  // X = B[perm]
-  PRRP_TRY(launch_gather_rows(Bsrc, ldb, perm, tmp, nrhs, n, nrhs, st));
-  PRRP_TRY(launch_fill_u64(flags, (size_t)nb + 8, 0ull, st));
-  PRRP_TRY(launch_trsv_blocked(LU, n, lda, tmp, nrhs, nrhs, 1, flags, ticket, 1u, st));
-  PRRP_TRY(launch_fill_u64(flags, (size_t)nb + 8, 0ull, st));
-  PRRP_TRY(launch_trsv_blocked(LU, n, lda, tmp, nrhs, nrhs, 0, flags, ticket, 1u, st));
-  // copy out (row strides may differ)
-  PRRP_TRY(hipMemcpy2DAsync(X, ldx * 8, tmp, nrhs * 8, nrhs * 8, n, hipMemcpyDeviceToDevice, st));
+  SolveWs w(ws, n, nrhs);
+  PRRP_TRY(launch_gather_rows(Bsrc, ldb, perm, w.t1, nrhs, n, nrhs, st));
+  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.t2), (size_t)n * nrhs, kKeySent, st));
+  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.ticket), 1, 0ull, st));
+  PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t1, w.t2, nrhs, nrhs, 1, w.ticket, st));
+  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.t1), (size_t)n * nrhs, kKeySent, st));
+  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.ticket), 1, 0ull, st));
+  PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t2, w.t1, nrhs, nrhs, 0, w.ticket, st));
+  PRRP_TRY(hipMemcpy2DAsync(X, ldx * 8, w.t1, nrhs * 8, nrhs * 8, n, hipMemcpyDeviceToDevice, st));
   return 0;
 }
 }  // namespace
@@ -518,10 +624,9 @@ int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const
   if (ws_bytes < need) return -16;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
-  const int64_t nb = (n + 63) / 64;
-  size_t off = align_up((size_t)(nb + 8) * 8, 256);
-  double* R = reinterpret_cast<double*>(ws + off + align_up((size_t)n * nrhs * 8, 256));
-  double* mx = reinterpret_cast<double*>(ws + off + 2 * align_up((size_t)n * nrhs * 8, 256));
+  SolveWs w(ws, n, nrhs);
+  double* R = w.r;
+  double* mx = w.mx;
   int rc = solve_impl(LU, n, lda, perm, B, ldx, X, nrhs, ldx, ws, st);
   if (rc) return rc;
   std::vector<double> h(2 * nrhs);

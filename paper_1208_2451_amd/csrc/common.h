@@ -62,6 +62,60 @@ __device__ __forceinline__ void set_info(prrp_stats* st, int32_t v) {
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ------------------------------------------------ DPP lane permutations
+// Data-parallel-primitive moves between lanes (no LDS round trip).  Controls:
+// quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E, row_half_mirror
+// (lane i <-> 7-i within 8) = 0x141, row_mirror (i <-> 15-i within 16) = 0x140.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+// Sum over each aligned group of 8 lanes (every lane gets the group sum).
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  return v;
+}
+__device__ __forceinline__ uint64_t umax(uint64_t a, uint64_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint64_t max8_u64(uint64_t v) {
+  v = umax(v, dpp_u64<0xB1>(v));
+  v = umax(v, dpp_u64<0x4E>(v));
+  v = umax(v, dpp_u64<0x141>(v));
+  return v;
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+// Wave-wide max of a 64-bit key; the result is wave-uniform.
+__device__ __forceinline__ uint64_t wave_max_key(uint64_t v) {
+  v = max8_u64(v);
+  v = umax(v, dpp_u64<0x140>(v));          // rows of 16
+  return umax(umax(readlane_u64(v, 0), readlane_u64(v, 16)),
+              umax(readlane_u64(v, 32), readlane_u64(v, 48)));
+}
+// Wave-wide sum in a fixed order (bitwise reproducible); wave-uniform result.
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+  v = sum8(v);
+  v += dpp_d<0x140>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
 // ------------------------------------------------------ wave reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -5,9 +5,10 @@
 // for the two triangular solves of a panel step, written as products with
 // explicitly formed b x b factors (L21 = M^T (Pi11 L11), U12 = L11^-1 A12).
 //
-// Tile 128 x 128 per workgroup of 4 waves (2 x 2 waves of 64 x 64), K staged
-// through LDS 16 deep with the next K-slab prefetched into registers while the
-// current one is multiplied.  FP64 uses v_mfma_f64_16x16x4f64; the reduced
+// Tile BM x BN (128 x 128, or 64 x 64 for small or skinny products) per
+// workgroup of 4 waves (2 x 2), K staged through LDS 16 deep (32 for BF16)
+// with the next K-slab prefetched into registers while the current one is
+// multiplied.  FP64 uses v_mfma_f64_16x16x4f64; the reduced
 // precision Schur variants round the FP64 operands to FP32 or BF16 on their
 // way into LDS and use v_mfma_f32_16x16x4f32 / v_mfma_f32_16x16x32_bf16 with
 // FP32 accumulation; C stays FP64.
@@ -23,7 +24,7 @@
 namespace prrp {
 
 namespace {
-constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int BK = 16;
 constexpr int kGemmThreads = 256;
 constexpr int APAD = 4;   // LDS row padding (elements)
 
@@ -53,8 +54,9 @@ template <> __device__ __forceinline__ unsigned short conv<unsigned short>(doubl
 }  // namespace
 
 // T: LDS/operand element type (double, float, bf16 as unsigned short).
-template <typename T>
+template <typename T, int BM, int BN>
 __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
+  constexpr int WI = BM / 32, WJ = BN / 32;    // 16x16 blocks per wave
   // bf16 needs K multiples of 32 per MFMA; stage 32-deep slabs for it
   constexpr int KS = (sizeof(T) == 2) ? 32 : BK;
   __shared__ T As[2][KS][BM + APAD];
@@ -73,8 +75,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
   constexpr int AV = KS * BM / kGemmThreads;   // 8 (or 16 for bf16)
   constexpr int BV = KS * BN / kGemmThreads;
   double ra[AV], rb[BV];
-  // A: thread -> row (tid % BM... ) use: row = tid >> 1, k-chunk = (tid & 1) * AV
-  const int a_row = tid >> 1, a_k = (tid & 1) * AV;
+  const int a_row = tid / (KS / AV), a_k = (tid % (KS / AV)) * AV;
   const int b_k = tid / (BN / BV), b_n = (tid % (BN / BV)) * BV;
 
   auto load_slab = [&](int k0) {
@@ -98,12 +99,12 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
     for (int v = 0; v < BV; ++v) Bs[buf][b_k][b_n + v] = conv<T>(rb[v]);
   };
 
-  d4 accd[4][4];
-  f4 accf[4][4];
+  d4 accd[WI][WJ];
+  f4 accf[WI][WJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < WJ; ++j) {
       accd[i][j] = d4{0.0, 0.0, 0.0, 0.0};
       accf[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
@@ -119,50 +120,50 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
     if constexpr (sizeof(T) == 8) {
 #pragma unroll
       for (int kq = 0; kq < KS / 4; ++kq) {
-        double av[4], bv[4];
+        double av[WI], bv[WJ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = As[cur][kq * 4 + lk][wm * 64 + i * 16 + li];
+        for (int i = 0; i < WI; ++i) av[i] = As[cur][kq * 4 + lk][wm * (BM / 2) + i * 16 + li];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = Bs[cur][kq * 4 + lk][wn * 64 + j * 16 + li];
+        for (int j = 0; j < WJ; ++j) bv[j] = Bs[cur][kq * 4 + lk][wn * (BN / 2) + j * 16 + li];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WI; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < WJ; ++j)
             accd[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], accd[i][j], 0, 0, 0);
       }
     } else if constexpr (sizeof(T) == 4) {
 #pragma unroll
       for (int kq = 0; kq < KS / 4; ++kq) {
-        float av[4], bv[4];
+        float av[WI], bv[WJ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = As[cur][kq * 4 + lk][wm * 64 + i * 16 + li];
+        for (int i = 0; i < WI; ++i) av[i] = As[cur][kq * 4 + lk][wm * (BM / 2) + i * 16 + li];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = Bs[cur][kq * 4 + lk][wn * 64 + j * 16 + li];
+        for (int j = 0; j < WJ; ++j) bv[j] = Bs[cur][kq * 4 + lk][wn * (BN / 2) + j * 16 + li];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WI; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < WJ; ++j)
             accf[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], accf[i][j], 0, 0, 0);
       }
     } else {
       // bf16: one 16x16x32 MFMA per 32-deep slab; lane holds 8 consecutive k
-      s8 av[4], bv[4];
+      s8 av[WI], bv[WJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          av[i][t] = (short)As[cur][lk * 8 + t][wm * 64 + i * 16 + li];
-        }
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < WI; ++i)
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-          bv[j][t] = (short)Bs[cur][lk * 8 + t][wn * 64 + j * 16 + li];
+          av[i][t] = (short)As[cur][lk * 8 + t][wm * (BM / 2) + i * 16 + li];
         }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < WJ; ++j)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int t = 0; t < 8; ++t) {
+          bv[j][t] = (short)Bs[cur][lk * 8 + t][wn * (BN / 2) + j * 16 + li];
+        }
+#pragma unroll
+      for (int i = 0; i < WI; ++i)
+#pragma unroll
+        for (int j = 0; j < WJ; ++j)
           accf[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], accf[i][j], 0, 0, 0);
     }
     if (sl + 1 < nslab) {
@@ -174,13 +175,13 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
   // epilogue
   double amax = 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < WJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = m0 + wm * 64 + i * 16 + ((sizeof(T) == 8) ? (lk + 4 * v) : (4 * lk + v));
-        const int c = n0 + wn * 64 + j * 16 + li;
+        const int r = m0 + wm * (BM / 2) + i * 16 + ((sizeof(T) == 8) ? (lk + 4 * v) : (4 * lk + v));
+        const int c = n0 + wn * (BN / 2) + j * 16 + li;
         if (r < M && c < N) {
           const double p = (sizeof(T) == 8) ? accd[i][j][v] : (double)accf[i][j][v];
           double* cp = g.C + (int64_t)r * g.ldc + c;
@@ -202,16 +203,24 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
   }
 }
 
-hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream) {
-  if (a.M <= 0 || a.N <= 0) return hipSuccess;
+template <int BM, int BN>
+static hipError_t launch_tiles(const GemmArgs& a, hipStream_t stream) {
   dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
   if (a.prec == PRRP_SCHUR_FP32)
-    hipLaunchKernelGGL(gemm_kernel<float>, grid, dim3(kGemmThreads), 0, stream, a);
+    hipLaunchKernelGGL((gemm_kernel<float, BM, BN>), grid, dim3(kGemmThreads), 0, stream, a);
   else if (a.prec == PRRP_SCHUR_BF16)
-    hipLaunchKernelGGL(gemm_kernel<unsigned short>, grid, dim3(kGemmThreads), 0, stream, a);
+    hipLaunchKernelGGL((gemm_kernel<unsigned short, BM, BN>), grid, dim3(kGemmThreads), 0, stream, a);
   else
-    hipLaunchKernelGGL(gemm_kernel<double>, grid, dim3(kGemmThreads), 0, stream, a);
+    hipLaunchKernelGGL((gemm_kernel<double, BM, BN>), grid, dim3(kGemmThreads), 0, stream, a);
   return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream) {
+  if (a.M <= 0 || a.N <= 0) return hipSuccess;
+  // 128 x 128 tiles when they fill the chip twice over, else 64 x 64
+  const int64_t big = (int64_t)((a.M + 127) / 128) * ((a.N + 127) / 128);
+  if (big >= 512) return launch_tiles<128, 128>(a, stream);
+  return launch_tiles<64, 64>(a, stream);
 }
 
 }  // namespace prrp

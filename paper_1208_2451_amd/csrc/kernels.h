@@ -55,13 +55,14 @@ struct GeppArgs {
   int m;                      // panel rows
   const int32_t* sel;         // [bw] selected panel rows in slot order
   double* PL;                 // [bw][bw]  Pi11 L11 (row p11[j] = row j of L11)
-  double* Linv;               // [bw][bw]  L11^-1
   int32_t* mv_dst;            // [2 kMaxB] row moves: panel position <- panel row
   int32_t* mv_src;
   int32_t* n_moves;
   prrp_stats* stats;
 };
 hipError_t launch_gepp(const GeppArgs& a, hipStream_t stream);
+hipError_t launch_trsm_u12(double* A, int64_t lda, int64_t k0, int bw, int64_t nr, double* amax1,
+                           double* amax2, hipStream_t stream);
 
 struct MoveArgs {
   double* A;
@@ -102,9 +103,9 @@ hipError_t launch_init_factor(const double* A, int64_t n, int64_t lda, int64_t* 
 // -------------------------------------------------------------- solves
 hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm, double* X,
                               int64_t ldx, int64_t n, int64_t nrhs, hipStream_t s);
-hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, double* X, int64_t ldx,
-                               int64_t nrhs, int lower, uint64_t* flags, uint32_t* ticket,
-                               uint32_t epoch, hipStream_t s);
+hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, const double* Bin,
+                               double* Yout, int64_t ld, int64_t nrhs, int lower, uint32_t* ticket,
+                               hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double* X, int64_t ldx,
                            const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
                            hipStream_t s);

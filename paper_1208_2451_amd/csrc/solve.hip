@@ -3,9 +3,11 @@
 //
 // trsv_kernel: blocked triangular solve with many right-hand sides in one
 // launch.  Workgroups take 64-row blocks in dependency order from a ticket
-// counter; a block accumulates the products with already solved blocks as
-// their completion flags appear (release/acquire through device-scope
-// fences), then solves its diagonal block in one wave per right-hand side.
+// counter; a block accumulates the products with already solved blocks
+// (oldest first) as their values appear -- the output starts out holding a
+// sentinel and each value is written once with a device-scope store, so no
+// fences are needed -- then solves its diagonal block, one wave per
+// right-hand side.
 //
 // residual_kernel: r = b - A x with the error-free transformations TwoProduct
 // (by FMA) and TwoSum, accumulated per lane as in Ogita, Rump and Oishi's Dot2
@@ -41,9 +43,10 @@ hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm,
 
 template <bool LOWER>
 __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, int64_t lda,
-                                                   double* X, int64_t ldx, int64_t nrhs,
-                                                   uint64_t* flags, uint32_t* ticket,
-                                                   uint32_t epoch) {
+                                                   const double* Bin, double* Yout, int64_t ld,
+                                                   int64_t nrhs, uint32_t* ticket) {
+  // Yout starts out holding the sentinel; every solution value is written
+  // exactly once, so dependent blocks poll the values they need.
   __shared__ double D[NB][NB + 1];
   __shared__ double yj[NB][RC];
   __shared__ double part[4][NB][RC];
@@ -61,9 +64,15 @@ __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, 
   const int k = LOWER ? t : nb - 1 - t;
   const int64_t r0 = (int64_t)k * NB;
   const int rows = (int)min<int64_t>(NB, n - r0);
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, c = e % NB;
-    D[i][c] = (i < rows && c < rows) ? LU[(r0 + i) * lda + r0 + c] : 0.0;
+  {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = (tid >> 6) + 4 * u, c = tid & 63;
+      v[u] = (i < rows && c < rows) ? LU[(r0 + i) * lda + r0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) D[(tid >> 6) + 4 * u][tid & 63] = v[u];
   }
   const int ri = tid & 63, q = tid >> 6;      // row, column quarter
   for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RC) {
@@ -71,36 +80,41 @@ __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, 
     double acc[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) acc[r] = 0.0;
-    const int jb = LOWER ? 0 : k + 1;
-    const int je = LOWER ? k : nb;
-    for (int j = jb; j < je; ++j) {
-      if (tid == 0) {
-        unsigned it = 0;
-        while (ld_dev(&flags[j]) != (uint64_t)epoch) {
-          __builtin_amdgcn_s_sleep(2);
-          if (++it > kSpinLimit) { bad_s = 1; break; }
-        }
-        __threadfence();
-      }
-      __syncthreads();
-      if (bad_s) return;
+    // blocks this one depends on, oldest (earliest solved) first
+    const int nd = LOWER ? k : nb - 1 - k;
+    for (int d = 0; d < nd; ++d) {
+      const int j = LOWER ? d : nb - 1 - d;
       const int64_t c0 = (int64_t)j * NB;
       const int cols = (int)min<int64_t>(NB, n - c0);
+      int bad = 0;
       for (int e = tid; e < NB * RC; e += 256) {
         const int c = e / RC, r = e % RC;
-        yj[c][r] = (c < cols && r < nr) ? X[(c0 + c) * ldx + rc0 + r] : 0.0;
+        double v = 0.0;
+        if (c < cols && r < nr) {
+          const uint64_t* p = reinterpret_cast<const uint64_t*>(Yout + (c0 + c) * ld + rc0 + r);
+          uint64_t w = ld_dev(p);
+          unsigned it = 0;
+          while (w == kKeySent) {
+            __builtin_amdgcn_s_sleep(1);
+            w = ld_dev(p);
+            if (++it > kSpinLimit) { bad = 1; break; }
+          }
+          v = __longlong_as_double((long long)w);
+        }
+        yj[c][r] = v;
       }
+      if (bad) bad_s = 1;
       __syncthreads();
+      if (bad_s) return;
       if (ri < rows) {
         const double* lrow = LU + (r0 + ri) * lda + c0;
-#pragma unroll 4
-        for (int c = q * 16; c < q * 16 + 16; ++c) {
-          if (c < cols) {
-            const double l = lrow[c];
+        double l[16];
 #pragma unroll
-            for (int r = 0; r < RC; ++r) acc[r] = fma(l, yj[c][r], acc[r]);
-          }
-        }
+        for (int u = 0; u < 16; ++u) l[u] = (q * 16 + u < cols) ? lrow[q * 16 + u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+          for (int r = 0; r < RC; ++r) acc[r] = fma(l[u], yj[q * 16 + u][r], acc[r]);
       }
       __syncthreads();
     }
@@ -111,7 +125,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, 
     for (int r = wave; r < nr; r += 4) {
       double b = 0.0;
       if (lane < rows)
-        b = X[(r0 + lane) * ldx + rc0 + r] -
+        b = Bin[(r0 + lane) * ld + rc0 + r] -
             (part[0][lane][r] + part[1][lane][r] + part[2][lane][r] + part[3][lane][r]);
       if (LOWER) {
         for (int i = 0; i < rows; ++i) {
@@ -126,30 +140,30 @@ __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, 
           if (lane < i) b = fma(-D[lane][i], y, b);
         }
       }
-      if (lane < rows) X[(r0 + lane) * ldx + rc0 + r] = b;
+      if (lane < rows)
+        st_dev(reinterpret_cast<uint64_t*>(Yout + (r0 + lane) * ld + rc0 + r),
+               (uint64_t)__double_as_longlong(b));
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    __threadfence();
-    st_dev(&flags[k], (uint64_t)epoch);
-  }
 }
 
-hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, double* X, int64_t ldx,
-                               int64_t nrhs, int lower, uint64_t* flags, uint32_t* ticket,
-                               uint32_t epoch, hipStream_t s) {
+hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, const double* Bin,
+                               double* Yout, int64_t ld, int64_t nrhs, int lower, uint32_t* ticket,
+                               hipStream_t s) {
   const int nb = (int)((n + NB - 1) / NB);
   if (lower)
-    hipLaunchKernelGGL(trsv_kernel<true>, dim3(nb), dim3(256), 0, s, LU, n, lda, X, ldx, nrhs,
-                       flags, ticket, epoch);
+    hipLaunchKernelGGL(trsv_kernel<true>, dim3(nb), dim3(256), 0, s, LU, n, lda, Bin, Yout, ld,
+                       nrhs, ticket);
   else
-    hipLaunchKernelGGL(trsv_kernel<false>, dim3(nb), dim3(256), 0, s, LU, n, lda, X, ldx, nrhs,
-                       flags, ticket, epoch);
+    hipLaunchKernelGGL(trsv_kernel<false>, dim3(nb), dim3(256), 0, s, LU, n, lda, Bin, Yout, ld,
+                       nrhs, ticket);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------ residual
+// The error-free transformations below must not be contracted into FMAs.
+#pragma clang fp contract(off)
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
   s = a + b;
   const double bb = s - a;

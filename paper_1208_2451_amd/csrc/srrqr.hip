@@ -36,20 +36,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRowGroups = kThreads / 8;
 
-__device__ __forceinline__ double rd8(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  return v;
-}
-__device__ __forceinline__ uint64_t max8(uint64_t v) {
-  uint64_t w;
-  w = __shfl_xor(v, 1, 64); v = w > v ? w : v;
-  w = __shfl_xor(v, 2, 64); v = w > v ? w : v;
-  w = __shfl_xor(v, 4, 64); v = w > v ? w : v;
-  return v;
-}
-
 // Poll a posted word until the sentinel is replaced; bounded.
 __device__ __forceinline__ uint64_t poll_word(const uint64_t* p, const uint32_t* abort_flag,
                                               int* bad) {
@@ -68,7 +54,7 @@ __device__ __forceinline__ uint64_t poll_word(const uint64_t* p, const uint32_t*
 struct Smem {
   double* R;       // R11 packed by columns: R(i,j), i <= j, at j(j+1)/2 + i
   double* vsh;     // [kMaxB] reflector / exchange vector
-  double* prow;    // [kMaxB] winner's row
+  double* prow;    // [2 kMaxB] winner's row, zero past bw (unguarded reads)
   double* rdiag;   // [kMaxB] 1 / R(i,i)
   double* scal;    // [8]   beta, gamma, ...
   uint64_t* red;   // [16]  reduction scratch
@@ -79,19 +65,20 @@ struct Smem {
 }  // namespace
 
 size_t srrqr_smem_bytes(int bw) {
-  return sizeof(double) * (size_t)(bw * (bw + 1) / 2 + 3 * kMaxB + 8) + sizeof(uint64_t) * 16 +
+  return sizeof(double) * (size_t)(bw * (bw + 1) / 2 + 4 * kMaxB + 8) + sizeof(uint64_t) * 16 +
          sizeof(int) * (kMaxB + 8);
 }
 
 template <int CPT, int RPT>
-__global__ __launch_bounds__(kThreads) void srrqr_kernel(SrrqrArgs a) {
+__global__ __launch_bounds__(kThreads, 1)
+void srrqr_kernel(SrrqrArgs a) {
   extern __shared__ double smem_raw[];
   const int bw = a.bw;
   Smem S;
   S.R = smem_raw;
   S.vsh = S.R + bw * (bw + 1) / 2;
   S.prow = S.vsh + kMaxB;
-  S.rdiag = S.prow + kMaxB;
+  S.rdiag = S.prow + 2 * kMaxB;
   S.scal = S.rdiag + kMaxB;
   S.red = reinterpret_cast<uint64_t*>(S.scal + 8);
   S.selpos = reinterpret_cast<int*>(S.red + 16);
@@ -154,22 +141,47 @@ __global__ __launch_bounds__(kThreads) void srrqr_kernel(SrrqrArgs a) {
 
   int bad = 0;
   const bool multi = G > 1;
+  S.prow[tid] = 0.0;             // 256 threads cover 2 kMaxB entries
+  __syncthreads();
 
   // ================================================================ QR steps
+  // Step s: (1) every wave rebuilds reflector H_{s-1} from the winner row of
+  // step s-1 (in LDS) and applies it to its unselected rows; (2) squared
+  // norms of the trailing parts, best candidate of the workgroup (barrier);
+  // (3) post it, and every wave polls the G posted keys itself; (4) the
+  // winning row is brought into LDS (barrier).
   for (int s = 0; s <= bw; ++s) {
-    // (a) apply reflector H_{s-1} to the unselected rows
     if (s > 0) {
-      const double beta = S.scal[0];
+      const int sp = s - 1;
+      const int c0 = sp + lane, c1 = sp + lane + 64;
+      const double x0 = S.prow[c0];           // zero past bw
+      const double x1 = S.prow[c1];
+      const double tail = wave_sum_fixed((lane == 0 ? 0.0 : x0 * x0) + x1 * x1);  // c > sp
+      const double head = S.prow[sp];
+      const double nrm = sqrt(fma(head, head, tail));
+      const double alpha = (nrm == 0.0) ? 0.0 : -copysign(nrm, head);
+      const double v0 = head - alpha;
+      const double vtv = fma(v0, v0, tail);
+      const double beta = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+      if (wave == 1) {
+        for (int i = lane; i < sp; i += 64) S.R[sp * (sp + 1) / 2 + i] = S.prow[i];
+        if (lane == 0) S.R[sp * (sp + 1) / 2 + sp] = alpha;
+      }
       double vr[CPT];
 #pragma unroll
-      for (int k = 0; k < CPT; ++k) vr[k] = (l8 + 8 * k < bw) ? S.vsh[l8 + 8 * k] : 0.0;
+      for (int k = 0; k < CPT; ++k) vr[k] = S.prow[l8 + 8 * k];    // all loads first
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        const int c = l8 + 8 * k;
+        vr[k] = (c > sp) ? vr[k] : (c == sp ? v0 : 0.0);
+      }
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         if (live[q] && !chosen[q]) {
           double d = 0.0;
 #pragma unroll
           for (int k = 0; k < CPT; ++k) d = fma(vr[k], x[q][k], d);
-          d = rd8(d);
+          d = sum8(d);
           const double f = beta * d;
 #pragma unroll
           for (int k = 0; k < CPT; ++k) x[q][k] = fma(-f, vr[k], x[q][k]);
@@ -178,8 +190,8 @@ __global__ __launch_bounds__(kThreads) void srrqr_kernel(SrrqrArgs a) {
     }
     if (s == bw) break;
 
-    // (b) pick this step's pivot
-    int p;              // tile position of the pivot
+    int p;              // tile position of this step's pivot
+    int wbad = 0;
     if (a.mode == 0) {
       uint64_t best = 0;
 #pragma unroll
@@ -190,20 +202,20 @@ __global__ __launch_bounds__(kThreads) void srrqr_kernel(SrrqrArgs a) {
           const int c = l8 + 8 * k;
           nu += (c >= s && c < bw) ? x[q][k] * x[q][k] : 0.0;
         }
-        nu = rd8(nu);
+        nu = sum8(nu);
         const uint64_t key = (live[q] && !chosen[q]) ? make_key(nu, (uint32_t)tpos[q]) : 0ull;
         best = key > best ? key : best;
       }
-      best = wave_max_u64(best);
+      best = wave_max_key(best);
       if (lane == 0) S.red[wave] = best;
       __syncthreads();
       uint64_t wkey = S.red[0];
 #pragma unroll
-      for (int i = 1; i < kThreads / 64; ++i) wkey = S.red[i] > wkey ? S.red[i] : wkey;
+      for (int i = 1; i < kThreads / 64; ++i) wkey = umax(wkey, S.red[i]);
       uint64_t gkey = wkey;
       uint64_t* post_r = slots + (size_t)s * round_stride;
       if (multi) {
-        // post my candidate (key + row); the owner's 8 lanes write the row
+        // post my candidate: the owner's 8 lanes write the row, then the key
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
           if (wkey != 0 && live[q] && !chosen[q] && (uint32_t)tpos[q] == key_index(wkey)) {
@@ -211,42 +223,33 @@ __global__ __launch_bounds__(kThreads) void srrqr_kernel(SrrqrArgs a) {
             for (int k = 0; k < CPT; ++k) {
               const int c = l8 + 8 * k;
               if (c < bw)
-                st_dev(post_r + (size_t)w * kPostW + 2 + c,
-                       (uint64_t)__double_as_longlong(x[q][k]));
+                st_dev(post_r + (size_t)w * kPostW + 2 + c, (uint64_t)__double_as_longlong(x[q][k]));
             }
           }
         }
         if (tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
-        __syncthreads();   // S.red reuse below
+        // every wave polls all G keys
         uint64_t kv = 0;
-        if (tid < G) kv = poll_word(post_r + (size_t)tid * kPostW, a.abort_flag, &bad);
-        kv = wave_max_u64(kv);
-        if (lane == 0) S.red[4 + wave] = kv;
-        if (bad) S.flags[0] = 1;
-        __syncthreads();
-        gkey = S.red[4];
-#pragma unroll
-        for (int i = 1; i < kThreads / 64; ++i) gkey = S.red[4 + i] > gkey ? S.red[4 + i] : gkey;
-        if (S.flags[0]) break;
+        for (int m = lane; m < G; m += 64) kv = umax(kv, poll_word(post_r + (size_t)m * kPostW, a.abort_flag, &wbad));
+        gkey = wave_max_key(kv);
       }
-      if (gkey == 0) {       // fewer rows than columns: cannot happen for valid tiles
+      if (gkey == 0 && !wbad) {      // fewer rows than columns: not a valid tile
         if (tid == 0) set_info(a.stats, -2);
-        break;
+        wbad = 1;
       }
       if (key_nonfinite(gkey) && tid == 0) set_info(a.stats, -1);
-      if ((gkey >> kDropBits) == 0) {   // exactly zero residual: rank deficient
-        if (tid == 0) {
-          S.flags[1] = 1;
-          if (a.report_rank) set_info(a.stats, (int32_t)(a.k0 + s + 1));
-        }
+      if ((gkey >> kDropBits) == 0 && tid == 0) {     // exactly zero residual
+        S.flags[1] = 1;
+        if (a.report_rank) set_info(a.stats, (int32_t)(a.k0 + s + 1));
       }
       p = (int)key_index(gkey);
     } else {
       p = a.sel_in[s];
     }
 
-    // (c) bring the pivot row into LDS
-    const int owner = p / a.rpw;
+    // bring the pivot row into LDS
+    int owner = p / a.rpw;
+    if (owner >= G || wbad) owner = G;           // only after a failed wait
     uint64_t* post_r = slots + (size_t)s * round_stride;
     if (owner == w) {
 #pragma unroll
@@ -264,40 +267,16 @@ __global__ __launch_bounds__(kThreads) void srrqr_kernel(SrrqrArgs a) {
           chosen[q] = true;
         }
       }
-    } else {
+    } else if (owner < G) {
       if (tid < bw) {
-        const uint64_t v = poll_word(post_r + (size_t)owner * kPostW + 2 + tid, a.abort_flag, &bad);
+        const uint64_t v = poll_word(post_r + (size_t)owner * kPostW + 2 + tid, a.abort_flag, &wbad);
         S.prow[tid] = __longlong_as_double((long long)v);
       }
-      if (bad) S.flags[0] = 1;
     }
+    if (wbad) S.flags[0] = 1;
     if (tid == 0) S.selpos[s] = p;
     __syncthreads();
     if (S.flags[0]) break;
-
-    // (d) reflector from prow[s:bw); R column s
-    if (wave == 0) {
-      const int c0 = s + lane, c1 = s + lane + 64;
-      const double x0 = (c0 < bw) ? S.prow[c0] : 0.0;
-      const double x1 = (c1 < bw) ? S.prow[c1] : 0.0;
-      const double tail = wave_sum((lane == 0 ? 0.0 : x0 * x0) + x1 * x1);  // sum over c > s
-      const double head = S.prow[s];
-      const double nrm = sqrt(fma(head, head, tail));
-      const double alpha = (nrm == 0.0) ? 0.0 : -copysign(nrm, head);
-      const double v0 = head - alpha;
-      const double vtv = fma(v0, v0, tail);
-      if (c0 < bw) S.vsh[c0] = (lane == 0) ? v0 : x0;
-      if (c1 < bw) S.vsh[c1] = x1;
-      if (lane == 0) {
-        S.scal[0] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-        S.R[s * (s + 1) / 2 + s] = alpha;
-      }
-      if (lane < s && lane < bw) S.vsh[lane] = 0.0;
-      if (lane + 64 < s && lane + 64 < bw) S.vsh[lane + 64] = 0.0;
-    } else if (wave == 1) {
-      for (int i = lane; i < s; i += 64) S.R[s * (s + 1) / 2 + i] = S.prow[i];
-    }
-    __syncthreads();
   }
 
   if (S.flags[0]) {
@@ -325,11 +304,11 @@ __global__ __launch_bounds__(kThreads) void srrqr_kernel(SrrqrArgs a) {
         const int i = 8 * kk + li;
         if (i >= bw) continue;
         double rcol[CPT];
+        // R(c, i) for c < i; the unguarded reads stay inside the packed array
 #pragma unroll
-        for (int k = 0; k <= kk; ++k) {
-          const int c = l8 + 8 * k;
-          rcol[k] = (c < i) ? S.R[i * (i + 1) / 2 + c] : 0.0;
-        }
+        for (int k = 0; k <= kk; ++k) rcol[k] = S.R[i * (i + 1) / 2 + l8 + 8 * k];
+#pragma unroll
+        for (int k = 0; k <= kk; ++k) rcol[k] = (l8 + 8 * k < i) ? rcol[k] : 0.0;
         const double di = S.rdiag[i];
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
@@ -361,13 +340,13 @@ __global__ __launch_bounds__(kThreads) void srrqr_kernel(SrrqrArgs a) {
               sk = kk2 > sk ? kk2 : sk;
             }
           }
-          sk = max8(sk);
+          sk = max8_u64(sk);
           if (live[q] && !chosen[q]) {
             const uint64_t rk = ((sk >> kDropBits) << kDropBits) | (kIdxMask - (uint32_t)tpos[q]);
             if (rk > best) { best = rk; best_slot = (int)key_index(sk); }
           }
         }
-        const uint64_t wbest = wave_max_u64(best);
+        const uint64_t wbest = wave_max_key(best);
         if (lane == 0) S.red[wave] = wbest;
         __syncthreads();
         uint64_t wkey = S.red[0];
