@@ -329,9 +329,18 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
   c.cap = std::min(256, device_cus());
   c.L = make_layout(n, b, method, tile_rows);
   PRRP_TRY(srrqr_prepare());
+  int height = 0;
+  if (method == 1) {
+    // tallest tournament: the first panel has the most tiles
+    const Tiles t0 = tile_bounds(n, tile_rows, std::min<int64_t>(b, n));
+    const int nt = (int)t0.start.size();
+    if (tree == PRRP_TREE_BINARY) { while ((1 << height) < nt) ++height; }
+    else height = nt - 1;
+  }
   {
     PhaseScope ps(6, c.st);
-    PRRP_TRY(launch_init_factor(A, n, lda, perm, stats, c.abort_flag(), c.st));
+    PRRP_TRY(launch_init_factor(A, n, lda, perm, stats, c.abort_flag(), height,
+                                (int)((n + b - 1) / b), c.st));
     PRRP_TRY(launch_fill_u64(c.slot_set(0), 2 * c.L.slots_set_words, kKeySent, c.st));
   }
 

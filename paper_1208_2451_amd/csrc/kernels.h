@@ -98,7 +98,8 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream);
 // -------------------------------------------------------------- misc
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
 hipError_t launch_init_factor(const double* A, int64_t n, int64_t lda, int64_t* perm,
-                              prrp_stats* stats, uint32_t* abort_flag, hipStream_t s);
+                              prrp_stats* stats, uint32_t* abort_flag, int tree_height, int panels,
+                              hipStream_t s);
 
 // -------------------------------------------------------------- solves
 hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm, double* X,

@@ -19,7 +19,7 @@ hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void init_stats_kernel(prrp_stats* st, uint32_t* abort_flag) {
+__global__ void init_stats_kernel(prrp_stats* st, uint32_t* abort_flag, int tree_height, int panels) {
   if (threadIdx.x == 0) {
     st->max_abs_A = 0.0;
     st->max_abs_W = 0.0;
@@ -27,8 +27,8 @@ __global__ void init_stats_kernel(prrp_stats* st, uint32_t* abort_flag) {
     st->max_block_L = 0.0;
     st->swaps = 0;
     st->info = 0;
-    st->tree_height = 0;
-    st->panels = 0;
+    st->tree_height = tree_height;
+    st->panels = panels;
     *abort_flag = 0u;
   }
 }
@@ -56,8 +56,10 @@ __global__ __launch_bounds__(256) void init_factor_kernel(const double* A, int64
 }
 
 hipError_t launch_init_factor(const double* A, int64_t n, int64_t lda, int64_t* perm,
-                              prrp_stats* stats, uint32_t* abort_flag, hipStream_t s) {
-  hipLaunchKernelGGL(init_stats_kernel, dim3(1), dim3(64), 0, s, stats, abort_flag);
+                              prrp_stats* stats, uint32_t* abort_flag, int tree_height, int panels,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(init_stats_kernel, dim3(1), dim3(64), 0, s, stats, abort_flag, tree_height,
+                     panels);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   int64_t blocks = (n * n + 255) / 256;
