@@ -135,6 +135,67 @@ Layout make_layout(int64_t n, int b, int method, int64_t tile_rows) {
 
 inline int herr(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
 
+// ------------------------------------------------ look-ahead side stream
+// The far part of each Schur update runs on a side stream whose CU mask
+// leaves PRRP_RESERVE_CUS (default 32) CUs free, so that the next panel's
+// latency-bound kernels (strong RRQR, GEPP) on the caller's stream always
+// find free CUs and run concurrently with it.
+struct SideStream {
+  int dev = -1;
+  hipStream_t s = nullptr;
+  hipStream_t main = nullptr;   // non-blocking stream carrying the panel chain
+  hipEvent_t ev[8] = {};
+  int next = 0;
+};
+SideStream g_side;
+
+bool lookahead_enabled() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = getenv("PRRP_LOOKAHEAD");
+    on = (e && atoi(e) == 0) ? 0 : 1;
+  }
+  return on == 1;
+}
+
+hipError_t side_stream(hipStream_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (g_side.s && g_side.dev == dev) { *out = g_side.s; return hipSuccess; }
+  const char* env = getenv("PRRP_RESERVE_CUS");
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  int reserve = env ? atoi(env) : 32;
+  if (reserve < 0) reserve = 0;
+  if (reserve > cus / 2) reserve = cus / 2;
+  std::vector<uint32_t> mask((cus + 31) / 32, 0u);
+  for (int c = 0; c < cus - reserve; ++c) mask[c / 32] |= 1u << (c % 32);
+  hipStream_t s = nullptr;
+  if (reserve == 0 ||
+      hipExtStreamCreateWithCUMask(&s, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  for (auto& ev : g_side.ev) {
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  e = hipStreamCreateWithFlags(&g_side.main, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  g_side.s = s;
+  g_side.dev = dev;
+  *out = s;
+  return hipSuccess;
+}
+
+hipEvent_t side_event() {
+  hipEvent_t e = g_side.ev[g_side.next];
+  g_side.next = (g_side.next + 1) & 7;
+  return e;
+}
+
 // ------------------------------------------------------------ phase timer
 struct PhaseTimer {
   bool on = false;
@@ -201,6 +262,8 @@ struct Ctx {
   int prev_ngroups = 0, prev_G = 0, prev_bw = 0;
   int32_t* prev_rounds = nullptr;
   int cap = 256;
+  hipStream_t side = nullptr;        // look-ahead stream (null: no look-ahead)
+  hipEvent_t far_event = nullptr;    // pending far Schur update on `side`
 
   uint64_t* slot_set(int parity) {
     return reinterpret_cast<uint64_t*>(ws + L.off_slots) + (size_t)parity * L.slots_set_words;
@@ -260,6 +323,11 @@ struct Ctx {
       e = launch_gepp(ga, st);
     }
     if (e != hipSuccess) return e;
+    if (far_event != nullptr) {
+      e = hipStreamWaitEvent(st, far_event, 0);
+      if (e != hipSuccess) return e;
+      far_event = nullptr;
+    }
     MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, (m > bw) ? Y() : nullptr, b};
     {
       PhaseScope ps(2, st);
@@ -282,13 +350,38 @@ struct Ctx {
         e = launch_trsm_u12(A, lda, k0, bw, nr, &stats->max_abs_U, &stats->max_abs_W, st);
       }
       if (e != hipSuccess) return e;
-      GemmArgs sc{(int)(m - bw), (int)nr, bw, A + (k0 + bw) * lda + k0, lda, a12, lda,
-                  A + (k0 + bw) * lda + k0 + bw, lda, -1.0, 1.0, &stats->max_abs_W, nullptr, schur};
+      // Schur update: the next panel's columns on this stream, the rest on
+      // the side stream (look-ahead) or here
+      const int64_t n_near = (side != nullptr) ? std::min<int64_t>(b, nr) : nr;
+      double* l21p = A + (k0 + bw) * lda + k0;
+      double* a22 = A + (k0 + bw) * lda + k0 + bw;
+      hipEvent_t e_u12 = nullptr;
+      if (side != nullptr && nr > n_near) {
+        e_u12 = side_event();
+        e = hipEventRecord(e_u12, st);
+        if (e != hipSuccess) return e;
+      }
+      GemmArgs sc{(int)(m - bw), (int)n_near, bw, l21p, lda, a12, lda, a22, lda, -1.0, 1.0,
+                  &stats->max_abs_W, nullptr, schur};
       {
         PhaseScope ps(5, st);
         e = launch_gemm(sc, st);
       }
       if (e != hipSuccess) return e;
+      if (e_u12 != nullptr) {
+        e = hipStreamWaitEvent(side, e_u12, 0);
+        if (e != hipSuccess) return e;
+        GemmArgs sc_far{(int)(m - bw), (int)(nr - n_near), bw, l21p, lda, a12 + n_near, lda,
+                        a22 + n_near, lda, -1.0, 1.0, &stats->max_abs_W, nullptr, schur};
+        {
+          PhaseScope ps(5, side);
+          e = launch_gemm(sc_far, side);
+        }
+        if (e != hipSuccess) return e;
+        far_event = side_event();
+        e = hipEventRecord(far_event, side);
+        if (e != hipSuccess) return e;
+      }
     }
     return hipSuccess;
   }
@@ -329,6 +422,18 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
   c.cap = std::min(256, device_cus());
   c.L = make_layout(n, b, method, tile_rows);
   PRRP_TRY(srrqr_prepare());
+  hipStream_t caller = c.st;
+  if (lookahead_enabled() && n > 2 * b) {
+    // The panel chain runs on an internal non-blocking stream and the far
+    // Schur updates on the side stream; both start after earlier work on the
+    // caller's stream, which in turn waits for both at the end.
+    PRRP_TRY(side_stream(&c.side));
+    hipEvent_t e0 = side_event();
+    PRRP_TRY(hipEventRecord(e0, caller));
+    PRRP_TRY(hipStreamWaitEvent(c.side, e0, 0));
+    PRRP_TRY(hipStreamWaitEvent(g_side.main, e0, 0));
+    c.st = g_side.main;
+  }
   int height = 0;
   if (method == 1) {
     // tallest tournament: the first panel has the most tiles
@@ -439,6 +544,12 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
       PRRP_TRY(c.srrqr(r));
     }
     PRRP_TRY(c.finish_panel(k0, bw));
+  }
+  if (c.far_event != nullptr) PRRP_TRY(hipStreamWaitEvent(c.st, c.far_event, 0));
+  if (c.st != caller) {
+    hipEvent_t e1 = side_event();
+    PRRP_TRY(hipEventRecord(e1, c.st));
+    PRRP_TRY(hipStreamWaitEvent(caller, e1, 0));
   }
   return 0;
 }

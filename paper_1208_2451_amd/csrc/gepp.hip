@@ -9,7 +9,11 @@
 //      the i-th selected row" (i = 0..bw-1), reduced to a list of whole-row
 //      moves (destination position <- source row);
 //   2. GEPP of the gathered block (selected rows in slot order) with the tie
-//      rule; its interchanges are folded into the moves of the top bw rows;
+//      rule, blocked by 8 columns: one wave factors each 8-column sub-panel in
+//      registers (rows keep their slots; only their position labels move),
+//      the block's interchanges and U block are applied column-parallel, and
+//      a rank-8 update follows; the interchanges are folded into the moves of
+//      the top bw rows;
 //   3. outputs: L11\U11 written into A's diagonal block and PL = Pi11 L11 (so
 //      that L21 = M^T PL, the point form of the block L = (R11^-1 R12)^T).
 // moves_kernel: applies the moves to the columns outside the panel, to perm,
@@ -24,22 +28,32 @@ namespace {
 constexpr int kGeppThreads = 256;
 }
 
+// Register "arrays" of a wave, two entries per lane (index e -> lane e & 63,
+// slot e >> 6), read with readlane and written by a lane select, always with
+// wave-uniform indices (no LDS round trips in the sequential plan).
+struct LaneArr {
+  int lo, hi;
+  __device__ __forceinline__ int get(int e) const {
+    return (e < 64) ? __builtin_amdgcn_readlane(lo, e) : __builtin_amdgcn_readlane(hi, e - 64);
+  }
+  __device__ __forceinline__ void set(int e, int v, int lane) {
+    if (e < 64) lo = (lane == e) ? v : lo;
+    else hi = (lane == e - 64) ? v : hi;
+  }
+};
+
 __global__ __launch_bounds__(kGeppThreads) void gepp_kernel(GeppArgs a) {
   extern __shared__ double sm[];
   const int bw = a.bw;
   const int ld = bw + 1;
-  double* D = sm;                          // [bw][ld]
-  double* lcol = D + bw * ld;              // [kMaxB]
-  double* xcol = lcol + kMaxB;             // [kMaxB]
-  uint64_t* red = reinterpret_cast<uint64_t*>(xcol + kMaxB);   // [8]
-  int* topAt = reinterpret_cast<int*>(red + 8);   // [kMaxB]
-  int* posTop = topAt + kMaxB;             // [kMaxB]
-  int* recIdx = posTop + kMaxB;            // [kMaxB]
-  int* dstq = recIdx + kMaxB;              // [kMaxB]
-  int* dsrc = dstq + kMaxB;                // [kMaxB]
-  int* p11 = dsrc + kMaxB;                 // [kMaxB]
-  int* ssel = p11 + kMaxB;                 // [kMaxB] selection (slot order)
-  int* misc = ssel + kMaxB;                // [8]
+  double* D = sm;                               // [bw][ld]
+  int* ssel = reinterpret_cast<int*>(D + bw * ld);   // [kMaxB] selection, slot order
+  int* p11 = ssel + kMaxB;                      // [kMaxB] slot at each final position
+  int* topAt = p11 + kMaxB;                     // [kMaxB] plan: panel row at top position
+  int* dstq = topAt + kMaxB;                    // [kMaxB] plan: displaced destinations
+  int* dsrc = dstq + kMaxB;                     // [kMaxB] plan: displaced sources
+  int* ipivb = dsrc + kMaxB;                    // [8] interchanges of the current block
+  int* misc = ipivb + 8;                        // [8]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
 
@@ -48,8 +62,7 @@ __global__ __launch_bounds__(kGeppThreads) void gepp_kernel(GeppArgs a) {
     if (tid < bw) ssel[tid] = a.sel[tid];
   }
   __syncthreads();
-  // gather the selected rows (panel part) in slot order; all loads of a
-  // thread are issued before the first LDS store
+  // gather the selected rows (panel part) in slot order; loads before stores
   {
     const int ty = tid >> 4, tx = tid & 15;
     double v[8][8];
@@ -71,90 +84,172 @@ __global__ __launch_bounds__(kGeppThreads) void gepp_kernel(GeppArgs a) {
         if (i < bw && c < bw) D[i * ld + c] = v[u][w];
       }
   }
-  // transposition plan (sequential; one lane)
-  if (tid == 0) {
-    for (int i = 0; i < bw; ++i) { topAt[i] = i; posTop[i] = i; }
+  // transposition plan, one wave in registers
+  if (wave == 0) {
+    LaneArr top{lane, lane + 64}, pos{lane, lane + 64}, rec{0, 0}, dq{0, 0}, ds{0, 0};
     int nd = 0;
     for (int i = 0; i < bw; ++i) {
-      const int r = ssel[i];
-      const int q = (r < bw) ? posTop[r] : r;
+      const int r = __builtin_amdgcn_readfirstlane(ssel[i]);
+      const int q = (r < bw) ? pos.get(r) : r;
       if (q == i) continue;
-      const int d = topAt[i];
-      topAt[i] = r;
-      if (r < bw) posTop[r] = i;
+      const int d = top.get(i);
+      top.set(i, r, lane);
+      if (r < bw) pos.set(r, i, lane);
       if (q < bw) {
-        topAt[q] = d;
-        posTop[d] = q;
+        top.set(q, d, lane);
+        pos.set(d, q, lane);
       } else {
         int k;
         if (r < bw) {
-          k = recIdx[r];
+          k = rec.get(r);
         } else {
           k = nd++;
-          dstq[k] = q;
+          dq.set(k, q, lane);
         }
-        dsrc[k] = d;
-        recIdx[d] = k;
-        posTop[d] = q;
+        ds.set(k, d, lane);
+        rec.set(d, k, lane);
+        pos.set(d, q, lane);
       }
     }
-    misc[0] = nd;
+    topAt[lane] = top.lo;
+    topAt[lane + 64] = top.hi;
+    dstq[lane] = dq.lo;
+    dstq[lane + 64] = dq.hi;
+    dsrc[lane] = ds.lo;
+    dsrc[lane + 64] = ds.hi;
+    if (lane == 0) misc[0] = nd;
   }
   __syncthreads();
 
-  // ------------------------------------------------------------- GEPP
-  double umax = 0.0;
-  for (int j = 0; j < bw; ++j) {
+  // ------------------------------------------------ blocked GEPP (8 columns)
+  for (int J = 0; J < bw; J += 8) {
+    const int jb = min(8, bw - J);
     if (wave == 0) {
-      const int i0 = j + lane, i1 = j + lane + 64;
-      const double d0 = D[min(i0, bw - 1) * ld + j], d1 = D[min(i1, bw - 1) * ld + j];
-      uint64_t k0 = (i0 < bw) ? make_key(fabs(d0), (uint32_t)i0) : 0ull;
-      uint64_t k1 = (i1 < bw) ? make_key(fabs(d1), (uint32_t)i1) : 0ull;
-      uint64_t kk = wave_max_key(k0 > k1 ? k0 : k1);
-      if (lane == 0) {
-        const int piv = (int)key_index(kk);
-        misc[1] = piv;
-        if ((kk >> kDropBits) == 0) {
-          if (a.stats) set_info(a.stats, (int32_t)(a.k0 + j + 1));
+      // (a) sub-panel rows J.. in registers: lane holds rows J+lane, J+lane+64
+      double p[2][8];
+      int ps[2];                          // current position of each held row
+      bool hv[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int r = J + lane + 64 * s;
+        hv[s] = r < bw;
+        ps[s] = r;
+        const int rr = hv[s] ? r : J;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) p[s][c] = D[rr * ld + J + (c < jb ? c : 0)];
+      }
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        if (jj >= jb) break;
+        const int col = J + jj;
+        uint64_t best = 0;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const uint64_t k = (hv[s] && ps[s] >= col) ? make_key(fabs(p[s][jj]), (uint32_t)ps[s]) : 0ull;
+          best = umax(best, k);
         }
-        if (key_nonfinite(kk) && a.stats) set_info(a.stats, -1);
-        const int t = p11[j]; p11[j] = p11[piv]; p11[piv] = t;
+        const uint64_t kk = wave_max_key(best);
+        const int piv = (int)key_index(kk);
+        if (lane == 0) {
+          if ((kk >> kDropBits) == 0 && a.stats) set_info(a.stats, (int32_t)(a.k0 + col + 1));
+          if (key_nonfinite(kk) && a.stats) set_info(a.stats, -1);
+          ipivb[jj] = piv;
+          const int t = p11[col]; p11[col] = p11[piv]; p11[piv] = t;
+        }
+        // the row holding position piv becomes position col and vice versa
+        const bool w0 = hv[0] && ps[0] == piv, w1 = hv[1] && ps[1] == piv;
+        const uint64_t bal0 = __ballot(w0), bal1 = __ballot(w1);
+        const int wl = bal0 ? (int)__builtin_ctzll(bal0) : (int)__builtin_ctzll(bal1);
+        const int wslot = bal0 ? 0 : 1;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          if (hv[s] && ps[s] == col) ps[s] = piv;
+          else if (hv[s] && ps[s] == piv) ps[s] = col;
+        }
+        // pivot row values (uniform)
+        double u[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) u[c] = readlane_d(wslot ? p[1][c] : p[0][c], wl);
+        const double pv = u[jj];
+        if (pv != 0.0) {
+          const double inv = 1.0 / pv;
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            if (hv[s] && ps[s] > col) {
+              const double l = p[s][jj] * inv;
+              p[s][jj] = l;
+#pragma unroll
+              for (int c = jj + 1; c < 8; ++c) p[s][c] = fma(-l, u[c], p[s][c]);
+            }
+          }
+        }
+      }
+      // write the sub-panel back at the rows' final positions
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        if (hv[s]) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            if (c < jb) D[ps[s] * ld + J + c] = p[s][c];
+        }
       }
     }
     __syncthreads();
-    const int piv = misc[1];
-    if (piv != j && tid < bw) {
-      const double t = D[j * ld + tid];
-      D[j * ld + tid] = D[piv * ld + tid];
-      D[piv * ld + tid] = t;
+    // (b) the block's interchanges on the other columns, then (c) the U block
+    //     U(J:J+jb, J+jb:) = L(J:J+jb, J:J+jb)^-1 (...), one thread per column
+    for (int c = tid; c < bw; c += kGeppThreads) {
+      if (c >= J && c < J + jb) continue;
+      for (int jj = 0; jj < jb; ++jj) {
+        const int pj = ipivb[jj];
+        if (pj != J + jj) {
+          const double t0 = D[(J + jj) * ld + c];
+          D[(J + jj) * ld + c] = D[pj * ld + c];
+          D[pj * ld + c] = t0;
+        }
+      }
+      if (c >= J + jb) {
+        double x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = (i < jb) ? D[(J + i) * ld + c] : 0.0;
+#pragma unroll
+        for (int i = 1; i < 8; ++i) {
+          if (i < jb) {
+            double acc = x[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) acc = fma(-D[(J + i) * ld + J + k], x[k], acc);
+            x[i] = acc;
+            D[(J + i) * ld + c] = acc;
+          }
+        }
+      }
     }
     __syncthreads();
-    const double pv = D[j * ld + j];
-    const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
-    if (tid > j && tid < bw) lcol[tid] = D[tid * ld + j] * inv;
-    __syncthreads();
-    if (pv != 0.0) {
-      // each wave sweeps whole row segments (contiguous LDS); four rows per
-      // batch with every read issued before the first write
-      const int c0 = j + lane, c1 = j + 64 + lane;
-      const bool in0 = c0 < bw, in1 = c1 < bw;
-      const int c0c = in0 ? c0 : 0, c1c = in1 ? c1 : 0;
-      const double u0 = D[j * ld + c0c], u1 = D[j * ld + c1c];
-      for (int i0 = j + 1 + wave; i0 < bw; i0 += 16) {
-        double l[4], a0[4], a1[4];
+    // (d) rank-jb update of the trailing block
+    const int t0 = J + jb;
+    if (t0 < bw) {
+      const int ty = tid >> 4, tx = tid & 15;
+      for (int i0 = t0 + ty; i0 < bw; i0 += 64) {
+        double lv[4][8];
+        int ii[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int ic = min(i0 + 4 * t, bw - 1);
-          l[t] = lcol[ic];
-          a0[t] = D[ic * ld + c0c];
-          a1[t] = D[ic * ld + c1c];
+        for (int a4 = 0; a4 < 4; ++a4) {
+          ii[a4] = i0 + 16 * a4;
+          const int ic = min(ii[a4], bw - 1);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) lv[a4][k] = (k < jb) ? D[ic * ld + J + k] : 0.0;
         }
+        for (int c0 = t0 + tx; c0 < bw; c0 += 16) {
+          double uv[8];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int i = i0 + 4 * t;
-          if (i < bw) {
-            if (in0) D[i * ld + c0] = (c0 == j) ? l[t] : fma(-l[t], u0, a0[t]);
-            if (in1) D[i * ld + c1] = fma(-l[t], u1, a1[t]);
+          for (int k = 0; k < 8; ++k) uv[k] = (k < jb) ? D[(J + k) * ld + c0] : 0.0;
+          double cv[4];
+#pragma unroll
+          for (int a4 = 0; a4 < 4; ++a4) cv[a4] = D[min(ii[a4], bw - 1) * ld + c0];
+#pragma unroll
+          for (int a4 = 0; a4 < 4; ++a4) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cv[a4] = fma(-lv[a4][k], uv[k], cv[a4]);
+            if (ii[a4] < bw) D[ii[a4] * ld + c0] = cv[a4];
           }
         }
       }
@@ -163,6 +258,7 @@ __global__ __launch_bounds__(kGeppThreads) void gepp_kernel(GeppArgs a) {
   }
 
   // ------------------------------------------- outputs: LU11, PL, moves
+  double umax = 0.0;
   for (int i = tid >> 4; i < bw; i += 16) {
     for (int c = tid & 15; c < bw; c += 16) {
       const double v = D[i * ld + c];
@@ -190,12 +286,10 @@ __global__ __launch_bounds__(kGeppThreads) void gepp_kernel(GeppArgs a) {
       atomic_max_pos(&a.stats->max_abs_W, umax);
     }
   }
-
 }
 
 size_t gepp_smem_bytes(int bw) {
-  return sizeof(double) * (size_t)(bw * (bw + 1) + 2 * kMaxB) + sizeof(uint64_t) * 8 +
-         sizeof(int) * (7 * kMaxB + 8);
+  return sizeof(double) * (size_t)(bw * (bw + 1)) + sizeof(int) * (5 * kMaxB + 16);
 }
 
 hipError_t launch_gepp(const GeppArgs& a, hipStream_t stream) {
@@ -254,11 +348,26 @@ __global__ __launch_bounds__(kMoveThreads) void moves_kernel(MoveArgs a) {
     if (cvalid && a.mv_dst[t] != a.mv_src[t]) a.A[(a.k0 + a.mv_dst[t]) * a.lda + col] = buf[t][cc];
   if (blockIdx.x == 0) {
     for (int t = tid; t < nm; t += kMoveThreads) a.perm[a.k0 + a.mv_dst[t]] = pbuf[t];
-    // Y rows: displaced rows (moves past the top block) carry their M columns
-    if (a.Y) {
-      for (int t = a.bw; t < nm; ++t) {
-        for (int c = tid; c < a.bw; c += kMoveThreads)
-          a.Y[(int64_t)a.mv_dst[t] * a.ldy + c] = a.Y[(int64_t)a.mv_src[t] * a.ldy + c];
+  }
+  // Y rows: displaced rows (moves past the top block) carry their M columns;
+  // spread over the workgroups, loads of a batch issued before its stores
+  if (a.Y) {
+    const int nd = nm - a.bw;
+    const int64_t total = (int64_t)nd * a.bw;
+    const int64_t stride = (int64_t)gridDim.x * kMoveThreads;
+    for (int64_t e0 = blockIdx.x * (int64_t)kMoveThreads + tid; e0 < total; e0 += 8 * stride) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = e0 + u * stride;
+        const int t = a.bw + (int)(e / a.bw), c = (int)(e % a.bw);
+        v[u] = (e < total) ? a.Y[(int64_t)a.mv_src[t] * a.ldy + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = e0 + u * stride;
+        const int t = a.bw + (int)(e / a.bw), c = (int)(e % a.bw);
+        if (e < total) a.Y[(int64_t)a.mv_dst[t] * a.ldy + c] = v[u];
       }
     }
   }
@@ -314,10 +423,17 @@ __global__ __launch_bounds__(256) void trsm_u12_kernel(double* A, int64_t lda, i
       const int i = 8 * kk + li;
       if (i >= bw) break;
       const double xi = __shfl(x[kk], (lane & ~7) | li, 64);
+      double lv[16];
+      // L(r, i) for r > i; unguarded reads stay inside the packed array
 #pragma unroll
       for (int k = kk; k < 16; ++k) {
         const int r = l8 + 8 * k;
-        if (r > i && r < bw) x[k] = fma(-Lp[r * (r - 1) / 2 + i], xi, x[k]);
+        lv[k] = Lp[r * (r - 1) / 2 + i];
+      }
+#pragma unroll
+      for (int k = kk; k < 16; ++k) {
+        const int r = l8 + 8 * k;
+        if (r > i && r < bw) x[k] = fma(-lv[k], xi, x[k]);
       }
     }
   }

@@ -178,10 +178,10 @@ void srrqr_kernel(SrrqrArgs a) {
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         if (live[q] && !chosen[q]) {
-          double d = 0.0;
+          double dd[4] = {0.0, 0.0, 0.0, 0.0};     // independent chains
 #pragma unroll
-          for (int k = 0; k < CPT; ++k) d = fma(vr[k], x[q][k], d);
-          d = sum8(d);
+          for (int k = 0; k < CPT; ++k) dd[k & 3] = fma(vr[k], x[q][k], dd[k & 3]);
+          const double d = sum8((dd[0] + dd[1]) + (dd[2] + dd[3]));
           const double f = beta * d;
 #pragma unroll
           for (int k = 0; k < CPT; ++k) x[q][k] = fma(-f, vr[k], x[q][k]);
@@ -196,13 +196,13 @@ void srrqr_kernel(SrrqrArgs a) {
       uint64_t best = 0;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        double nu = 0.0;
+        double nn[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
           const int c = l8 + 8 * k;
-          nu += (c >= s && c < bw) ? x[q][k] * x[q][k] : 0.0;
+          nn[k & 3] = (c >= s && c < bw) ? fma(x[q][k], x[q][k], nn[k & 3]) : nn[k & 3];
         }
-        nu = sum8(nu);
+        const double nu = sum8((nn[0] + nn[1]) + (nn[2] + nn[3]));
         const uint64_t key = (live[q] && !chosen[q]) ? make_key(nu, (uint32_t)tpos[q]) : 0ull;
         best = key > best ? key : best;
       }
