@@ -49,6 +49,25 @@ def srrqr_flops(n: int, b: int) -> float:
     return tot
 
 
+def measured_traffic(kernel_source: str, summary: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
+        src = open(os.path.join(ROOT, "paper_1208_2451_amd", "csrc", kernel_source), "rb").read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if "=" in line and line.startswith("    "):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_prefix") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -90,9 +109,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--solves", type=int, default=200)
+    ap.add_argument("--host-matrix", action="store_true",
+                    help="build the kappa matrix with NumPy on the host (same recipe) and copy it "
+                         "in, instead of building it with device QR")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy (neg of the n x n FP64 matrix, 2 n^2 8 bytes) "
+                         "first, as the scale for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU; this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU; the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -104,13 +129,21 @@ def main():
 
     n, b, tau = args.n, args.b, args.tau
     dev = torch.device("cuda:0")
-    log("generating kappa=1e6 matrix n=%d on the GPU" % n)
-    A0 = inputs.kappa_matrix(n, args.seed, 1e6, device="cuda:0")
+    if args.host_matrix:
+        log("generating kappa=1e6 matrix n=%d on the host" % n)
+        A0 = torch.from_numpy(inputs.kappa_matrix(n, args.seed, 1e6)).to(dev)
+    else:
+        log("generating kappa=1e6 matrix n=%d on the GPU" % n)
+        A0 = inputs.kappa_matrix(n, args.seed, 1e6, device="cuda:0")
     B = torch.from_numpy(inputs.rhs(n, args.seed, 1)).to(dev)
     A = torch.empty_like(A0)
     ws = torch.empty(_lib.workspace_size(n, b, 0, 0), dtype=torch.uint8, device=dev)
     sws = torch.empty(_lib.solve_workspace_size(n, 1), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        torch.neg(A0, out=A)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written" % (8 * n * n, 8 * n * n))
 
     x_ref = None
     if not args.no_accuracy:
@@ -200,9 +233,13 @@ def main():
     else:
         fl = srrqr_flops(n, b)
         ach = fl / (ph[dom] * 1e-3) / 1e12
+        traffic = None
+        if dom == "srrqr" and (n, b) == (8192, 128):
+            traffic = measured_traffic("srrqr.hip", "hbm_counters_srrqr_n8192_b128_fp64.md")
         roof = {"kernel": "%s" % {"srrqr": "srrqr_kernel (strong RRQR panel)", "gepp": "gepp_kernel"}.get(dom, dom),
                 "bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
-                "frac": ach / PEAK_TFLOPS["fp64"], "traffic": None,
+                "frac": ach / PEAK_TFLOPS["fp64"], "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                 "algorithmic": "2 m b^2 - 2/3 b^3 flops per panel (Appendix C), %.4g per factorization" % fl,
                 "note": "latency bound: b dependent pivot steps per panel"}
     roof["launches_per_factor"] = hv["phase_launches_per_factor"].get(dom)

@@ -19,7 +19,7 @@ and reselected by strong RRQR; the root's rows are the pivots.  The panel is
 then factored by QR without pivoting of its transpose with the pivot rows
 first, L_2j = (R11^-1 R12)^T, and the step continues as in LU_PRRP.
 
-Readings (listed in the design doc): Pi_j is applied LAPACK-style as the sequence of
+Readings: Pi_j is applied LAPACK-style as the sequence of
 transpositions row k0+i <-> current position of the i-th selected row; tiles
 hold ``tile_rows`` rows except a last remainder of at most b rows, which joins
 the previous tile; a tree node stacks the left child's candidates over the
@@ -27,9 +27,11 @@ right child's, each in increasing row order; an odd node is promoted; the flat
 tree stacks the running candidates over the next whole tile.
 
 Pinned by tests/test_oracle_lu.py (b = 1 equals LAPACK getrf, A[perm] = LU,
-|L_2j| <= tau, per-step growth bound, Wilkinson/Foster/Wright growth printed
-in the paper or given in closed form, CALU_PRRP with one tile equals LU_PRRP,
-node certificates and the per-step (1 + tau b)^(H+1) bound).
+|L_2j| <= tau, per-step growth bound, Wilkinson and Foster growth printed in
+the paper or given in closed form, CALU_PRRP with one tile equals LU_PRRP,
+node certificates and the per-step (1 + tau b)^(H+1) bound).  The growth 1
+printed for the Wright matrix is not used as a pin: with either reading of
+exp(M h) (exact, or its first-order form) the last pivot of U is 2.
 """
 from __future__ import annotations
 

@@ -4,10 +4,10 @@ Follows Appendix A ("Strong RRQR"): first a classical QR with column pivoting of
 B^T = P^T, then, while some |(R11^-1 R12)_ij| exceeds tau, interchange the
 selected column i with the unselected column j and re-triangularise R.  The
 columns of P^T are the rows of the panel P, so the selected columns are the
-panel's pivot rows (Section 2.1: "strong RRQR factorization on the transpose of
-the first panel ... to identify ... b pivot rows").
+panel's pivot rows (Section 2.1 picks a panel's b pivot rows by strong RRQR of
+the panel's transpose).
 
-Readings where the paper is silent (also listed in the design doc):
+Readings where the paper is silent:
   * QRCP recomputes the squared norm of every candidate's trailing part at each
     step (no norm downdating) and picks by ``rules.argmax_lowest``.
   * The exchange loop picks the violating entry of largest magnitude (tie rule:
