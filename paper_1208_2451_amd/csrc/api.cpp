@@ -681,14 +681,14 @@ struct SolveWs {
 int solve_impl(const double* LU, int64_t n, int64_t lda, const int64_t* perm, const double* Bsrc,
                int64_t ldb, double* X, int64_t nrhs, int64_t ldx, char* ws, hipStream_t st) {
   SolveWs w(ws, n, nrhs);
-  PRRP_TRY(launch_gather_rows(Bsrc, ldb, perm, w.t1, nrhs, n, nrhs, st));
-  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.t2), (size_t)n * nrhs, kKeySent, st));
-  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.ticket), 1, 0ull, st));
-  PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t1, w.t2, nrhs, nrhs, 1, w.ticket, st));
-  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.t1), (size_t)n * nrhs, kKeySent, st));
-  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.ticket), 1, 0ull, st));
-  PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t2, w.t1, nrhs, nrhs, 0, w.ticket, st));
-  PRRP_TRY(hipMemcpy2DAsync(X, ldx * 8, w.t1, nrhs * 8, nrhs * 8, n, hipMemcpyDeviceToDevice, st));
+  // gather B[perm] into t1, sentinel into t2, zero both tickets
+  PRRP_TRY(launch_gather_rows(Bsrc, ldb, perm, w.t1, nrhs, n, nrhs, w.t2, nrhs, w.ticket, st));
+  // L y = t1 into t2; each block then fills its rows of X with the sentinel
+  // (B, which X may alias, has been read by the gather)
+  PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t1, nrhs, w.t2, nrhs, nrhs, 1, w.ticket, X, ldx, st));
+  // U x = y straight into X
+  PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t2, nrhs, X, ldx, nrhs, 0, w.ticket + 1, nullptr, 0,
+                               st));
   return 0;
 }
 }  // namespace

@@ -102,11 +102,16 @@ hipError_t launch_init_factor(const double* A, int64_t n, int64_t lda, int64_t* 
                               hipStream_t s);
 
 // -------------------------------------------------------------- solves
+// X = B[perm]; fills Y (nullable) with the sentinel and zeroes tickets[0..1].
 hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm, double* X,
-                              int64_t ldx, int64_t n, int64_t nrhs, hipStream_t s);
+                              int64_t ldx, int64_t n, int64_t nrhs, double* Y, int64_t ldy,
+                              uint32_t* tickets, hipStream_t s);
+// Blocked triangular solve; Yout must hold the sentinel on entry and *ticket
+// must be 0.  Fill (nullable) receives the sentinel, block by block, once a
+// block's rows of Bin have been consumed.
 hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, const double* Bin,
-                               double* Yout, int64_t ld, int64_t nrhs, int lower, uint32_t* ticket,
-                               hipStream_t s);
+                               int64_t ldb, double* Yout, int64_t ld, int64_t nrhs, int lower,
+                               uint32_t* ticket, double* Fill, int64_t ldf, hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double* X, int64_t ldx,
                            const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
                            hipStream_t s);

@@ -7,7 +7,7 @@
 // (oldest first) as their values appear -- the output starts out holding a
 // sentinel and each value is written once with a device-scope store, so no
 // fences are needed -- then solves its diagonal block, one wave per
-// right-hand side.
+// right-hand side, with the block's rows held in registers.
 //
 // residual_kernel: r = b - A x with the error-free transformations TwoProduct
 // (by FMA) and TwoSum, accumulated per lane as in Ogita, Rump and Oishi's Dot2
@@ -22,34 +22,41 @@ constexpr int NB = 64;
 constexpr int RC = 8;    // right-hand sides per pass
 }
 
+// X = B[perm] (row gather); also resets the solve's tickets and fills the
+// first solve's output Y with the sentinel.
 __global__ void gather_rows_kernel(const double* B, int64_t ldb, const int64_t* perm, double* X,
-                                   int64_t ldx, int64_t n, int64_t nrhs) {
+                                   int64_t ldx, int64_t n, int64_t nrhs, double* Y, int64_t ldy,
+                                   uint32_t* tickets) {
   const int64_t total = n * nrhs;
+  if (blockIdx.x == 0 && threadIdx.x < 2 && tickets) tickets[threadIdx.x] = 0u;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / nrhs, r = e - i * nrhs;
     X[i * ldx + r] = B[perm[i] * ldb + r];
+    if (Y) reinterpret_cast<uint64_t*>(Y)[i * ldy + r] = kKeySent;
   }
 }
 
 hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm, double* X,
-                              int64_t ldx, int64_t n, int64_t nrhs, hipStream_t s) {
+                              int64_t ldx, int64_t n, int64_t nrhs, double* Y, int64_t ldy,
+                              uint32_t* tickets, hipStream_t s) {
   int64_t blocks = (n * nrhs + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, B, ldb, perm, X,
-                     ldx, n, nrhs);
+                     ldx, n, nrhs, Y, ldy, tickets);
   return hipGetLastError();
 }
 
-template <bool LOWER>
+template <bool LOWER, int RCT>
 __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, int64_t lda,
-                                                   const double* Bin, double* Yout, int64_t ld,
-                                                   int64_t nrhs, uint32_t* ticket) {
+                                                   const double* Bin, int64_t ldb, double* Yout,
+                                                   int64_t ld, int64_t nrhs, uint32_t* ticket,
+                                                   double* Fill, int64_t ldf) {
   // Yout starts out holding the sentinel; every solution value is written
   // exactly once, so dependent blocks poll the values they need.
   __shared__ double D[NB][NB + 1];
-  __shared__ double yj[NB][RC];
-  __shared__ double part[4][NB][RC];
+  __shared__ double yj[NB][RCT];
+  __shared__ double part[4][NB][RCT];
   __shared__ int blk_s;
   __shared__ int bad_s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -75,20 +82,27 @@ __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, 
     for (int u = 0; u < 16; ++u) D[(tid >> 6) + 4 * u][tid & 63] = v[u];
   }
   const int ri = tid & 63, q = tid >> 6;      // row, column quarter
-  for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RC) {
-    const int nr = (int)min<int64_t>(RC, nrhs - rc0);
-    double acc[RC];
+  const int nd = LOWER ? k : nb - 1 - k;      // blocks this one depends on
+  for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RCT) {
+    const int nr = (int)min<int64_t>(RCT, nrhs - rc0);
+    double acc[RCT];
 #pragma unroll
-    for (int r = 0; r < RC; ++r) acc[r] = 0.0;
-    // blocks this one depends on, oldest (earliest solved) first
-    const int nd = LOWER ? k : nb - 1 - k;
+    for (int r = 0; r < RCT; ++r) acc[r] = 0.0;
+    // dependencies oldest (earliest solved) first; the L tile of a dependency
+    // is loaded before its solution values are waited for
     for (int d = 0; d < nd; ++d) {
       const int j = LOWER ? d : nb - 1 - d;
       const int64_t c0 = (int64_t)j * NB;
       const int cols = (int)min<int64_t>(NB, n - c0);
+      double l[16];
+      {
+        const double* lrow = LU + (r0 + (ri < rows ? ri : 0)) * lda + c0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) l[u] = (ri < rows && q * 16 + u < cols) ? lrow[q * 16 + u] : 0.0;
+      }
       int bad = 0;
-      for (int e = tid; e < NB * RC; e += 256) {
-        const int c = e / RC, r = e % RC;
+      for (int e = tid; e < NB * RCT; e += 256) {
+        const int c = e / RCT, r = e % RCT;
         double v = 0.0;
         if (c < cols && r < nr) {
           const uint64_t* p = reinterpret_cast<const uint64_t*>(Yout + (c0 + c) * ld + rc0 + r);
@@ -106,58 +120,78 @@ __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, 
       if (bad) bad_s = 1;
       __syncthreads();
       if (bad_s) return;
-      if (ri < rows) {
-        const double* lrow = LU + (r0 + ri) * lda + c0;
-        double l[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) l[u] = (q * 16 + u < cols) ? lrow[q * 16 + u] : 0.0;
+      for (int u = 0; u < 16; ++u)
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-#pragma unroll
-          for (int r = 0; r < RC; ++r) acc[r] = fma(l[u], yj[q * 16 + u][r], acc[r]);
-      }
+        for (int r = 0; r < RCT; ++r) acc[r] = fma(l[u], yj[q * 16 + u][r], acc[r]);
       __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < RC; ++r) part[q][ri][r] = acc[r];
+    for (int r = 0; r < RCT; ++r) part[q][ri][r] = acc[r];
     __syncthreads();
-    // one wave per right-hand side solves the diagonal block
+    // One wave per right-hand side solves the diagonal block.  Each lane keeps
+    // its row of the block in registers and takes the solved values by
+    // readlane, so a substitution step is one FMA and one lane read.
     for (int r = wave; r < nr; r += 4) {
-      double b = 0.0;
+      double drow[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) drow[i] = D[lane][i];
+      double bv = 0.0;
       if (lane < rows)
-        b = Bin[(r0 + lane) * ld + rc0 + r] -
-            (part[0][lane][r] + part[1][lane][r] + part[2][lane][r] + part[3][lane][r]);
+        bv = Bin[(r0 + lane) * ldb + rc0 + r] -
+             (part[0][lane][r] + part[1][lane][r] + part[2][lane][r] + part[3][lane][r]);
       if (LOWER) {
-        for (int i = 0; i < rows; ++i) {
-          const double y = __shfl(b, i, 64);
-          if (lane > i) b = fma(-D[lane][i], y, b);
+        // rows past the block's end hold zeros, so their steps change nothing
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const double y = readlane_d(bv, i);
+          const double upd = fma(-drow[i], y, bv);
+          bv = (lane > i) ? upd : bv;
         }
       } else {
-        for (int i = rows - 1; i >= 0; --i) {
-          const double bi = __shfl(b, i, 64);
-          const double y = bi / D[i][i];
-          if (lane == i) b = y;
-          if (lane < i) b = fma(-D[lane][i], y, b);
+        // quotient b_i / u_ii from the reciprocal and one exact-remainder
+        // correction (the remainder b - u y is exact under FMA), computed
+        // while the chain runs
+        const double dself = (lane < rows) ? D[lane][lane] : 1.0;
+        const double rinv = 1.0 / dself;
+#pragma unroll
+        for (int i = NB - 1; i >= 0; --i) {
+          const double bi = readlane_d(bv, i);
+          const double di = readlane_d(dself, i), rr = readlane_d(rinv, i);
+          double y = bi * rr;
+          y = fma(rr, fma(-di, y, bi), y);
+          const double upd = fma(-drow[i], y, bv);
+          bv = (lane < i) ? upd : ((lane == i) ? y : bv);
         }
       }
       if (lane < rows)
         st_dev(reinterpret_cast<uint64_t*>(Yout + (r0 + lane) * ld + rc0 + r),
-               (uint64_t)__double_as_longlong(b));
+               (uint64_t)__double_as_longlong(bv));
     }
     __syncthreads();
+  }
+  // the next solve's output starts out holding the sentinel (this block's rows)
+  if (Fill) {
+    for (int e = tid; e < rows * nrhs; e += 256) {
+      const int i = e / (int)nrhs, r = e - i * (int)nrhs;
+      reinterpret_cast<uint64_t*>(Fill)[(r0 + i) * ldf + r] = kKeySent;
+    }
   }
 }
 
 hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, const double* Bin,
-                               double* Yout, int64_t ld, int64_t nrhs, int lower, uint32_t* ticket,
-                               hipStream_t s) {
+                               int64_t ldb, double* Yout, int64_t ld, int64_t nrhs, int lower,
+                               uint32_t* ticket, double* Fill, int64_t ldf, hipStream_t s) {
   const int nb = (int)((n + NB - 1) / NB);
-  if (lower)
-    hipLaunchKernelGGL(trsv_kernel<true>, dim3(nb), dim3(256), 0, s, LU, n, lda, Bin, Yout, ld,
-                       nrhs, ticket);
-  else
-    hipLaunchKernelGGL(trsv_kernel<false>, dim3(nb), dim3(256), 0, s, LU, n, lda, Bin, Yout, ld,
-                       nrhs, ticket);
+#define PRRP_TRSV(LO, R)                                                                       \
+  hipLaunchKernelGGL((trsv_kernel<LO, R>), dim3(nb), dim3(256), 0, s, LU, n, lda, Bin, ldb, Yout, \
+                     ld, nrhs, ticket, Fill, ldf)
+  if (nrhs == 1) {
+    if (lower) PRRP_TRSV(true, 1); else PRRP_TRSV(false, 1);
+  } else {
+    if (lower) PRRP_TRSV(true, RC); else PRRP_TRSV(false, RC);
+  }
+#undef PRRP_TRSV
   return hipGetLastError();
 }
 
