@@ -126,6 +126,49 @@ int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const
                 const double* B, double* X, int64_t nrhs, int64_t ldx, double tol, int max_iter,
                 int* iters, double* final_rel, void* workspace, size_t ws_bytes, void* stream);
 
+/* prrp_refine with the whole loop enqueued on `stream` and no host
+ * synchronisation: the stopping test runs on the device and the kernels of
+ * later iterations return at once once it is met, so the call can be
+ * captured in a HIP graph.  At most max_iter (<= 1000) corrections.  iters
+ * (device int32, may be NULL) receives the number of corrections, final_rel
+ * (device double, may be NULL) the last max|D|/max|X|.  Results are identical
+ * to prrp_refine's for the same arguments. */
+int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
+                      const int64_t* perm, const double* B, double* X, int64_t nrhs, int64_t ldx,
+                      double tol, int max_iter, int32_t* iters, double* final_rel,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Batched LU_PRRP of `count` independent systems of uneven sizes (the
+ * algorithm of Section 2.1 on each).  A plan fixes the problems: A[i] (device,
+ * n[i] x n[i], row-major, lda[i]), panel width b[i], perm[i] (device, n[i]
+ * int64), stats + i (device array of count records), tau, the Schur
+ * precision and the rows per panel workgroup (64 or 128: fewer, fuller
+ * workgroups per strong RRQR step).  With A0 non-NULL each system is also
+ * refined after its factorization (as prrp_refine_async, tolerance tol, at
+ * most max_iter corrections): A0[i] the original matrix (lda[i]), B[i] and
+ * X[i] n[i] x nrhs[i] row-major.  The plan allocates and owns its device
+ * memory (work lists and per-problem workspaces) at creation, which returns
+ * 0 or -k for an invalid argument k, -1002 when device memory runs out.
+ * Running a plan enqueues, on `stream`, one launch per kernel per panel
+ * step over all problems still active, results equal to factoring each
+ * system alone with prrp_factor_mixed; with use_graph the sequence is
+ * captured into a HIP graph on the first run and replayed afterwards.  Plans
+ * hold no other state between runs; runs of one plan must not overlap. */
+int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
+                           const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
+                           int schur, int rows_per_wg, const double* const* A0,
+                           const double* const* B, double* const* X, const int64_t* nrhs,
+                           double tol, int max_iter, void** plan);
+int prrp_batch_plan_run(void* plan, void* stream, int use_graph);
+/* Copies the refinement iteration counts and last ratios (count each) to the
+ * host (synchronous; NULL skips). */
+int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels);
+int prrp_batch_plan_destroy(void* plan);
+/* One-shot batched factorization: create a plan, run it, wait, destroy it. */
+int prrp_factor_batched(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
+                        const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
+                        int schur, void* stream);
+
 /* C = alpha A B + beta C for row-major FP64 matrices (M x K, K x N, M x N),
  * computed by the MFMA kernel of the Schur-complement update (equation
  * "update", Section 2.1).  prec: a prrp_precision; with FP32 / BF16 the

@@ -8,8 +8,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
-__all__ = ["factor", "calu_factor", "solve", "residual", "refine", "gemm", "FactorResult",
-           "read_stats"]
+__all__ = ["factor", "calu_factor", "solve", "residual", "refine", "refine_async", "gemm",
+           "FactorResult", "read_stats", "BatchPlan"]
 
 
 def _torch():
@@ -154,6 +154,121 @@ def refine(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30, workspace=Non
                                   workspace.numel(), _stream_ptr())
     _lib.check(code, "prrp_refine")
     return X.view(B.shape), it.value, rel.value
+
+
+def refine_async(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30, workspace=None):
+    """Iterative refinement enqueued without host synchronisation.
+
+    Returns (X, iters, rel) where iters (int32) and rel (float64) are
+    one-element device tensors filled when the stream reaches them."""
+    from . import _lib
+    torch = _torch()
+    _check_matrix(A)
+    n = A.shape[0]
+    B2 = B.contiguous().view(n, -1)
+    nrhs = B2.shape[1]
+    X = torch.empty_like(B2)
+    ws_bytes = _lib.solve_workspace_size(n, nrhs)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc(ws_bytes, A.device)
+    it = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rel = torch.zeros(1, dtype=torch.float64, device=A.device)
+    code = _lib.lib().prrp_refine_async(A.data_ptr(), LU.data_ptr(), n, A.stride(0), perm.data_ptr(),
+                                        B2.data_ptr(), X.data_ptr(), nrhs, nrhs, float(tol),
+                                        int(max_iter), it.data_ptr(), rel.data_ptr(),
+                                        workspace.data_ptr(), workspace.numel(), _stream_ptr())
+    _lib.check(code, "prrp_refine_async")
+    return X.view(B.shape), it, rel
+
+
+class BatchPlan:
+    """Batched LU_PRRP (+ optional refinement) of systems of uneven sizes.
+
+    ``mats``: list of square float64 CUDA tensors factored in place.  With
+    ``originals``/``rhs`` given, each system is refined after its
+    factorization into the tensors of ``solutions``.  ``run()`` enqueues the
+    plan on the current stream (``graph=True`` captures it once into a HIP
+    graph and replays it afterwards)."""
+
+    def __init__(self, mats, bs, tau: float = 2.0, precision: str = "fp64", rows_per_wg: int = 64,
+                 originals=None, rhs=None, tol: float = 1e-14, max_iter: int = 10):
+        import ctypes
+        from . import _lib
+        torch = _torch()
+        count = len(mats)
+        if count < 1 or len(bs) != count:
+            raise ValueError("one panel width per matrix")
+        for M in mats:
+            _check_matrix(M)
+        dev = mats[0].device
+        self.mats = list(mats)
+        self.perms = [torch.empty(M.shape[0], dtype=torch.int64, device=dev) for M in mats]
+        self.stats_raw = torch.zeros(count * _lib.STATS_BYTES, dtype=torch.uint8, device=dev)
+        self.originals = originals
+        self.rhs = None
+        self.solutions = None
+        arr = lambda ct, vals: (ct * count)(*vals)  # noqa: E731
+        self._keep = []
+        pA = arr(ctypes.c_void_p, [M.data_ptr() for M in mats])
+        pn = arr(ctypes.c_int64, [M.shape[0] for M in mats])
+        plda = arr(ctypes.c_int64, [M.stride(0) for M in mats])
+        pb = arr(ctypes.c_int, [int(b) for b in bs])
+        pperm = arr(ctypes.c_void_p, [p.data_ptr() for p in self.perms])
+        self._keep += [pA, pn, plda, pb, pperm]
+        pA0 = pB = pX = pnr = None
+        if originals is not None:
+            self.rhs = [r.contiguous().view(M.shape[0], -1) for r, M in zip(rhs, mats)]
+            self.solutions = [torch.empty_like(r) for r in self.rhs]
+            for O, M in zip(originals, mats):
+                _check_matrix(O, "original")
+                if O.stride(0) != M.stride(0):
+                    raise ValueError("original and factored matrices need equal leading dimensions")
+            pA0 = arr(ctypes.c_void_p, [O.data_ptr() for O in originals])
+            pB = arr(ctypes.c_void_p, [r.data_ptr() for r in self.rhs])
+            pX = arr(ctypes.c_void_p, [x.data_ptr() for x in self.solutions])
+            pnr = arr(ctypes.c_int64, [r.shape[1] for r in self.rhs])
+            self._keep += [pA0, pB, pX, pnr]
+        handle = ctypes.c_void_p(0)
+        code = _lib.lib().prrp_batch_plan_create(
+            count, pA, pn, plda, pb, pperm, self.stats_raw.data_ptr(), float(tau),
+            _lib.PRECISIONS[precision], int(rows_per_wg), pA0, pB, pX, pnr, float(tol),
+            int(max_iter), ctypes.byref(handle))
+        _lib.check(code, "prrp_batch_plan_create")
+        self._h = handle
+
+    def run(self, graph: bool = False):
+        from . import _lib
+        _lib.check(_lib.lib().prrp_batch_plan_run(self._h, _stream_ptr(), 1 if graph else 0),
+                   "prrp_batch_plan_run")
+
+    def stats(self, i: int) -> dict:
+        from . import _lib
+        w = _lib.STATS_BYTES
+        return read_stats(self.stats_raw[i * w:(i + 1) * w])
+
+    def refine_results(self):
+        """(iterations, last ratios) per system, copied to the host."""
+        import ctypes
+        from . import _lib
+        count = len(self.mats)
+        it = (ctypes.c_int32 * count)()
+        rel = (ctypes.c_double * count)()
+        _lib.check(_lib.lib().prrp_batch_plan_results(self._h, it, rel), "prrp_batch_plan_results")
+        return list(it), list(rel)
+
+    def close(self):
+        """Waits for the device, then frees the plan's memory."""
+        from . import _lib
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _torch().cuda.synchronize()
+            _lib.lib().prrp_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
 
 
 def gemm(A, B, C=None, alpha: float = 1.0, beta: float = 0.0, precision: str = "fp64"):

@@ -46,6 +46,14 @@ _SIGS = {
     "prrp_residual": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _vp]),
     "prrp_refine": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _dbl, _i32,
                            ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _sz, _vp]),
+    "prrp_refine_async": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _dbl, _i32,
+                                 _vp, _vp, _vp, _sz, _vp]),
+    "prrp_batch_plan_create": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, _i32,
+                                      _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(_vp)]),
+    "prrp_batch_plan_run": (_i32, [_vp, _vp, _i32]),
+    "prrp_batch_plan_results": (_i32, [_vp, _vp, _vp]),
+    "prrp_batch_plan_destroy": (_i32, [_vp]),
+    "prrp_factor_batched": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, _vp]),
     "prrp_gemm": (_i32, [_i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64, _dbl, _vp, _i64, _i32, _vp]),
     "prrp_profile_enable": (_i32, [_i32]),
     "prrp_profile_read": (_i32, [ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 #include <cstdlib>
 
@@ -84,9 +85,11 @@ int panel_wg_cap() {
   return cap;
 }
 
-int groups_for_rows(int64_t rows, int cap) {
+// `target` rows per workgroup (64 or 128); the workspace is always sized for
+// the default 64, which gives the most workgroups.
+int groups_for_rows(int64_t rows, int cap, int target = 64) {
   cap = std::min(cap, panel_wg_cap());
-  int G = (int)std::min<int64_t>(cap, (rows + 63) / 64);
+  int G = (int)std::min<int64_t>(cap, (rows + target - 1) / target);
   if (G < 1) G = 1;
   while ((rows + G - 1) / G > kRowsPerWgMax) ++G;
   const int64_t rpw = (rows + G - 1) / G;
@@ -262,6 +265,7 @@ struct Ctx {
   int prev_ngroups = 0, prev_G = 0, prev_bw = 0;
   int32_t* prev_rounds = nullptr;
   int cap = 256;
+  int rpw_target = 64;               // rows per panel workgroup (64 or 128)
   hipStream_t side = nullptr;        // look-ahead stream (null: no look-ahead)
   hipEvent_t far_event = nullptr;    // pending far Schur update on `side`
 
@@ -413,8 +417,10 @@ int validate_common(double* A, int64_t n, int64_t lda, int b, double tau, int64_
 
 int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau, int tree,
                int64_t tile_rows, int64_t* perm, prrp_stats* stats, void* workspace,
-               size_t ws_bytes, void* stream, int schur) {
+               size_t ws_bytes, void* stream, int schur, bool lookahead = true,
+               int rpw_target = 64) {
   Ctx c;
+  c.rpw_target = rpw_target;
   c.A = A; c.n = n; c.lda = lda; c.b = b; c.tau = tau; c.perm = perm; c.stats = stats;
   c.ws = static_cast<char*>(workspace);
   c.st = static_cast<hipStream_t>(stream);
@@ -423,7 +429,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
   c.L = make_layout(n, b, method, tile_rows);
   PRRP_TRY(srrqr_prepare());
   hipStream_t caller = c.st;
-  if (lookahead_enabled() && n > 2 * b) {
+  if (lookahead && lookahead_enabled() && n > 2 * b) {
     // The panel chain runs on an internal non-blocking stream and the far
     // Schur updates on the side stream; both start after earlier work on the
     // caller's stream, which in turn waits for both at the end.
@@ -457,7 +463,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
     if (method == 0 || t.start.size() == 1) {
       SrrqrArgs a = base_args(c, k0, bw);
       a.ngroups = 1;
-      a.G = groups_for_rows(m, c.cap);
+      a.G = groups_for_rows(m, c.cap, c.rpw_target);
       a.rpw = (int)((m + a.G - 1) / a.G);
       a.tile_start[0] = 0;
       a.tile_len[0] = (int)m;
@@ -479,7 +485,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
       if (tree == PRRP_TREE_BINARY) {
         SrrqrArgs a = base_args(c, k0, bw);
         a.ngroups = ntiles;
-        a.G = groups_for_rows(maxlen, c.cap);
+        a.G = groups_for_rows(maxlen, c.cap, c.rpw_target);
         a.rpw = (maxlen + a.G - 1) / a.G;
         for (int i = 0; i < ntiles; ++i) { a.tile_start[i] = t.start[i]; a.tile_len[i] = t.len[i]; }
         a.mode = 0;
@@ -492,7 +498,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
           PRRP_TRY(launch_build_lists(cur, level, bw, lists, nxt, pairs, -1, 0, c.st));
           SrrqrArgs nd = base_args(c, k0, bw);
           nd.ngroups = pairs;
-          nd.G = groups_for_rows(2 * bw, c.cap);
+          nd.G = groups_for_rows(2 * bw, c.cap, c.rpw_target);
           nd.rpw = (2 * bw + nd.G - 1) / nd.G;
           for (int i = 0; i < pairs; ++i) { nd.tile_start[i] = i * 2 * bw; nd.tile_len[i] = 2 * bw; }
           nd.row_list = lists;
@@ -506,7 +512,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
         // flat tree: running candidates stacked over each next whole tile
         SrrqrArgs a = base_args(c, k0, bw);
         a.ngroups = 1;
-        a.G = groups_for_rows(t.len[0], c.cap);
+        a.G = groups_for_rows(t.len[0], c.cap, c.rpw_target);
         a.rpw = (t.len[0] + a.G - 1) / a.G;
         a.tile_start[0] = t.start[0];
         a.tile_len[0] = t.len[0];
@@ -518,7 +524,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
           SrrqrArgs nd = base_args(c, k0, bw);
           const int len = bw + t.len[i];
           nd.ngroups = 1;
-          nd.G = groups_for_rows(len, c.cap);
+          nd.G = groups_for_rows(len, c.cap, c.rpw_target);
           nd.rpw = (len + nd.G - 1) / nd.G;
           nd.tile_start[0] = 0;
           nd.tile_len[0] = len;
@@ -532,7 +538,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
       // QR of the panel transpose with the winners as pivots (emits M)
       SrrqrArgs r = base_args(c, k0, bw);
       r.ngroups = 1;
-      r.G = groups_for_rows(m, c.cap);
+      r.G = groups_for_rows(m, c.cap, c.rpw_target);
       r.rpw = (int)((m + r.G - 1) / r.G);
       r.tile_start[0] = 0;
       r.tile_len[0] = (int)m;
@@ -658,8 +664,10 @@ int prrp_solve_workspace_size(int64_t n, int64_t nrhs, size_t* bytes) {
   if (n < 1 || n > kMaxN) return -1;
   if (nrhs < 1) return -2;
   if (!bytes) return -3;
-  // ticket | three n x nrhs vectors (two solve buffers, refinement residual) | maxima
-  *bytes = 256 + 3 * align_up((size_t)n * nrhs * 8, 256) + align_up((size_t)nrhs * 16 + 16, 256);
+  // tickets | three n x nrhs vectors (two solve buffers, refinement residual) |
+  // refinement state | maxima
+  *bytes = 256 + 3 * align_up((size_t)n * nrhs * 8, 256) + 256 +
+           align_up((size_t)nrhs * 16 + 16, 256);
   return 0;
 }
 
@@ -667,28 +675,33 @@ namespace {
 struct SolveWs {
   uint32_t* ticket;
   double *t1, *t2, *r, *mx;
+  IrState* ir;
   SolveWs(char* ws, int64_t n, int64_t nrhs) {
     const size_t v = align_up((size_t)n * nrhs * 8, 256);
     ticket = reinterpret_cast<uint32_t*>(ws);
     t1 = reinterpret_cast<double*>(ws + 256);
     t2 = reinterpret_cast<double*>(ws + 256 + v);
     r = reinterpret_cast<double*>(ws + 256 + 2 * v);
-    mx = reinterpret_cast<double*>(ws + 256 + 3 * v);
+    ir = reinterpret_cast<IrState*>(ws + 256 + 3 * v);
+    mx = reinterpret_cast<double*>(ws + 256 + 3 * v + 256);
   }
 };
 
 // X = U^-1 L^-1 B[perm]; X may alias B.
 int solve_impl(const double* LU, int64_t n, int64_t lda, const int64_t* perm, const double* Bsrc,
-               int64_t ldb, double* X, int64_t nrhs, int64_t ldx, char* ws, hipStream_t st) {
+               int64_t ldb, double* X, int64_t nrhs, int64_t ldx, char* ws, hipStream_t st,
+               const uint32_t* skip = nullptr) {
   SolveWs w(ws, n, nrhs);
   // gather B[perm] into t1, sentinel into t2, zero both tickets
-  PRRP_TRY(launch_gather_rows(Bsrc, ldb, perm, w.t1, nrhs, n, nrhs, w.t2, nrhs, w.ticket, st));
+  PRRP_TRY(launch_gather_rows(Bsrc, ldb, perm, w.t1, nrhs, n, nrhs, w.t2, nrhs, w.ticket, skip,
+                              st));
   // L y = t1 into t2; each block then fills its rows of X with the sentinel
   // (B, which X may alias, has been read by the gather)
-  PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t1, nrhs, w.t2, nrhs, nrhs, 1, w.ticket, X, ldx, st));
+  PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t1, nrhs, w.t2, nrhs, nrhs, 1, w.ticket, X, ldx, skip,
+                               st));
   // U x = y straight into X
   PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t2, nrhs, X, ldx, nrhs, 0, w.ticket + 1, nullptr, 0,
-                               st));
+                               skip, st));
   return 0;
 }
 }  // namespace
@@ -720,7 +733,7 @@ int prrp_residual(const double* A, int64_t n, int64_t lda, const double* X, cons
   if (!R) return -6;
   if (nrhs < 1) return -7;
   if (ldx < nrhs) return -8;
-  return herr(launch_residual(A, n, lda, X, ldx, B, ldx, R, ldx, nrhs,
+  return herr(launch_residual(A, n, lda, X, ldx, B, ldx, R, ldx, nrhs, nullptr,
                               static_cast<hipStream_t>(stream)));
 }
 
@@ -754,11 +767,11 @@ int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const
   int it = 0;
   double rel = INFINITY;
   for (it = 1; it <= max_iter; ++it) {
-    PRRP_TRY(launch_residual(A, n, lda, X, ldx, B, ldx, R, nrhs, nrhs, st));
+    PRRP_TRY(launch_residual(A, n, lda, X, ldx, B, ldx, R, nrhs, nrhs, nullptr, st));
     rc = solve_impl(LU, n, lda, perm, R, nrhs, R, nrhs, nrhs, ws, st);
     if (rc) return rc;
     PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(mx), 2 * nrhs, 0ull, st));
-    PRRP_TRY(launch_axpy_maxrel(X, ldx, R, nrhs, n, nrhs, mx, st));
+    PRRP_TRY(launch_axpy_maxrel(X, ldx, R, nrhs, n, nrhs, mx, nullptr, st));
     PRRP_TRY(hipMemcpyAsync(h.data(), mx, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     PRRP_TRY(hipStreamSynchronize(st));
     rel = 0.0;
@@ -772,6 +785,519 @@ int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const
   if (iters) *iters = std::min(it, max_iter);
   if (final_rel) *final_rel = rel;
   return 0;
+}
+
+int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
+                      const int64_t* perm, const double* B, double* X, int64_t nrhs, int64_t ldx,
+                      double tol, int max_iter, int32_t* iters, double* final_rel,
+                      void* workspace, size_t ws_bytes, void* stream) {
+  if (!A) return -1;
+  if (!LU) return -2;
+  if (n < 1 || n > kMaxN) return -3;
+  if (lda < n) return -4;
+  if (!perm) return -5;
+  if (!B) return -6;
+  if (!X) return -7;
+  if (nrhs < 1) return -8;
+  if (ldx < nrhs) return -9;
+  if (!(tol >= 0.0)) return -10;
+  if (max_iter < 0 || max_iter > 1000) return -11;
+  size_t need = 0;
+  prrp_solve_workspace_size(n, nrhs, &need);
+  if (!workspace) return -14;
+  if (ws_bytes < need) return -15;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  SolveWs w(ws, n, nrhs);
+  PRRP_TRY(launch_ir_init(w.ir, w.mx, nrhs, iters, final_rel, st));
+  int rc = solve_impl(LU, n, lda, perm, B, ldx, X, nrhs, ldx, ws, st);
+  if (rc) return rc;
+  const uint32_t* done = &w.ir->done;
+  for (int it = 1; it <= max_iter; ++it) {
+    PRRP_TRY(launch_residual(A, n, lda, X, ldx, B, ldx, w.r, nrhs, nrhs, done, st));
+    rc = solve_impl(LU, n, lda, perm, w.r, nrhs, w.r, nrhs, nrhs, ws, st, done);
+    if (rc) return rc;
+    PRRP_TRY(launch_axpy_maxrel(X, ldx, w.r, nrhs, n, nrhs, w.mx, done, st));
+    PRRP_TRY(launch_ir_check(w.ir, w.mx, nrhs, tol, max_iter, iters, final_rel, st));
+  }
+  return 0;
+}
+
+}  // extern "C"
+
+// ==========================================================================
+// Batched factorization of many independent systems (uneven sizes).
+//
+// A plan fixes the problems (pointers and sizes) and precomputes, for every
+// panel step, one work list per kernel: the strong-RRQR launch of a step
+// covers every problem still active (one group of workgroups per problem,
+// problems of equal panel width and workgroup count sharing a launch), and
+// the diagonal GEPP, row moves, L21 product, U12 solve and Schur update of
+// the step are one launch each over all active problems.  The plan owns its
+// device memory (work lists and per-problem workspaces, allocated at
+// creation).  Its launch sequence can be captured once into a HIP graph and
+// replayed; optional per-problem refinement runs on fork streams inside the
+// same sequence.
+// ==========================================================================
+namespace {
+
+struct PlanProblem {
+  double* A;
+  int64_t n, lda;
+  int b;
+  int64_t* perm;
+  prrp_stats* stats;
+  // plan-owned workspace
+  uint64_t* slots[2];
+  int32_t* rounds;        // [2]
+  int32_t* sel;           // [kMaxB]
+  double* Y;              // n x b
+  double* PL;             // b x b
+  int32_t* mv;            // 4 kMaxB + 4
+  int Gmax;
+  size_t set_words;
+  // refinement (A0 == nullptr: none)
+  const double* A0;
+  const double* B;
+  double* X;
+  int64_t nrhs;
+  char* sws;
+  size_t sws_bytes;
+};
+
+enum OpKind { OP_SRRQR = 0, OP_GEPP, OP_MOVES, OP_L21, OP_U12, OP_SCHUR };
+struct PlanOp {
+  OpKind kind;
+  size_t off;          // byte offset of the work list in plan memory
+  int count;
+  int bw;
+  int64_t max_a, max_b;
+  int prec;
+  int srrqr_index;     // OP_SRRQR: index into srrqr_args
+};
+
+struct BatchPlan {
+  int dev = 0;
+  double tau = 2.0;
+  int schur = 0;
+  int rpw_target = 64;
+  double tol = 0.0;
+  int max_iter = 0;
+  bool refine = false;
+  std::vector<PlanProblem> p;
+  char* dmem = nullptr;
+  size_t dbytes = 0;
+  uint64_t* slots_all = nullptr;
+  size_t slots_words = 0;
+  uint32_t* abort = nullptr;
+  int32_t* iters = nullptr;     // [count] refinement iterations
+  double* rels = nullptr;       // [count] last correction ratio
+  std::vector<PlanOp> ops;
+  std::vector<SrrqrArgs> srrqr_args;
+  int nforks = 0;
+  hipStream_t forks[4] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[4] = {};
+  hipStream_t cap = nullptr;     // private stream the graph is captured on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+hipError_t plan_enqueue(BatchPlan& P, hipStream_t st) {
+  hipError_t e;
+  for (auto& q : P.p) {
+    e = launch_init_factor(q.A, q.n, q.lda, q.perm, q.stats, P.abort, 0,
+                           (int)((q.n + q.b - 1) / q.b), st);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_fill_u64(P.slots_all, P.slots_words, kKeySent, st);
+  if (e != hipSuccess) return e;
+  for (const PlanOp& o : P.ops) {
+    char* list = P.dmem + o.off;
+    switch (o.kind) {
+      case OP_SRRQR: e = launch_srrqr(P.srrqr_args[o.srrqr_index], st); break;
+      case OP_GEPP: e = launch_gepp_batched(reinterpret_cast<GeppArgs*>(list), o.count, o.bw, st); break;
+      case OP_MOVES:
+        e = launch_moves_batched(reinterpret_cast<MoveArgs*>(list), o.count, o.max_a, st);
+        break;
+      case OP_L21:
+      case OP_SCHUR:
+        e = launch_gemm_batched(reinterpret_cast<GemmArgs*>(list), o.count, (int)o.max_a,
+                                (int)o.max_b, o.prec, st);
+        break;
+      case OP_U12:
+        e = launch_trsm_u12_batched(reinterpret_cast<TrsmArgs*>(list), o.count, o.bw, o.max_a, st);
+        break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  if (P.refine) {
+    e = hipEventRecord(P.ev_fork, st);
+    if (e != hipSuccess) return e;
+    for (int f = 0; f < P.nforks; ++f) {
+      e = hipStreamWaitEvent(P.forks[f], P.ev_fork, 0);
+      if (e != hipSuccess) return e;
+    }
+    for (size_t i = 0; i < P.p.size(); ++i) {
+      const PlanProblem& q = P.p[i];
+      if (!q.A0) continue;
+      hipStream_t fs = P.forks[i % P.nforks];
+      const int rc = prrp_refine_async(q.A0, q.A, q.n, q.lda, q.perm, q.B, q.X, q.nrhs, q.nrhs,
+                                       P.tol, P.max_iter, P.iters + i, P.rels + i, q.sws,
+                                       q.sws_bytes, fs);
+      if (rc != 0) return hipErrorInvalidValue;
+    }
+    for (int f = 0; f < P.nforks; ++f) {
+      e = hipEventRecord(P.ev_join[f], P.forks[f]);
+      if (e != hipSuccess) return e;
+      e = hipStreamWaitEvent(st, P.ev_join[f], 0);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+void plan_free(BatchPlan* P) {
+  if (!P) return;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  for (int f = 0; f < P->nforks; ++f) {
+    if (P->forks[f]) (void)hipStreamDestroy(P->forks[f]);
+    if (P->ev_join[f]) (void)hipEventDestroy(P->ev_join[f]);
+  }
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->cap) (void)hipStreamDestroy(P->cap);
+  if (P->dmem) (void)hipFree(P->dmem);
+  delete P;
+}
+
+}  // namespace
+
+extern "C" {
+
+int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
+                           const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
+                           int schur, int rows_per_wg, const double* const* A0,
+                           const double* const* B, double* const* X, const int64_t* nrhs,
+                           double tol, int max_iter, void** plan_out) {
+  if (count < 1 || count > 4096) return -1;
+  if (!A) return -2;
+  if (!n) return -3;
+  if (!lda) return -4;
+  if (!b) return -5;
+  if (!perm) return -6;
+  if (!stats) return -7;
+  if (!(tau > 1.0) || !std::isfinite(tau)) return -8;
+  if (schur < 0 || schur > 2) return -9;
+  if (rows_per_wg != 64 && rows_per_wg != 128) return -10;
+  const bool refine = A0 != nullptr;
+  if (refine && (!B || !X || !nrhs)) return -11;
+  if (refine && (!(tol >= 0.0) || max_iter < 0 || max_iter > 1000)) return -15;
+  if (!plan_out) return -17;
+  for (int64_t i = 0; i < count; ++i) {
+    if (!A[i] || !perm[i]) return -2;
+    if (n[i] < 1 || n[i] > kMaxN) return -3;
+    if (lda[i] < n[i]) return -4;
+    if (b[i] < 1 || b[i] > kMaxB || b[i] > n[i]) return -5;
+    if (refine && (!A0[i] || !B[i] || !X[i] || nrhs[i] < 1)) return -11;
+  }
+  PRRP_TRY(srrqr_prepare());
+  BatchPlan* P = new BatchPlan();
+  P->tau = tau;
+  P->schur = schur;
+  P->rpw_target = rows_per_wg;
+  P->refine = refine;
+  P->tol = tol;
+  P->max_iter = max_iter;
+  if (hipGetDevice(&P->dev) != hipSuccess) { delete P; return -1000; }
+  const int cap = std::min(256, device_cus());
+
+  // ---- per-problem workspaces.  Work lists below hold plan offsets in place
+  // of device pointers until relocation, with 0 meaning "none", so no real
+  // offset may be 0.
+  size_t off = 256;
+  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes, 256); return o; };
+  struct Offs { size_t slots, rounds, sel, y, pl, mv, sws; };
+  std::vector<Offs> po(count);
+  P->p.resize(count);
+  size_t slots_begin = 0, slots_end = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    PlanProblem& q = P->p[i];
+    q.A = A[i]; q.n = n[i]; q.lda = lda[i]; q.b = b[i]; q.perm = perm[i]; q.stats = stats + i;
+    q.Gmax = groups_for_rows(q.n, cap, 64);
+    q.set_words = (size_t)q.Gmax * kRoundsMax * kPostW;
+    po[i].slots = take(2 * q.set_words * 8);
+    if (i == 0) slots_begin = po[i].slots;
+    slots_end = off;
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    PlanProblem& q = P->p[i];
+    po[i].rounds = take(2 * 4);
+    po[i].sel = take(kMaxB * 4);
+    po[i].y = take((size_t)q.n * q.b * 8);
+    po[i].pl = take((size_t)q.b * q.b * 8);
+    po[i].mv = take((4 * kMaxB + 4) * 4);
+    q.A0 = nullptr;
+    if (refine) {
+      q.A0 = A0[i]; q.B = B[i]; q.X = X[i]; q.nrhs = nrhs[i];
+      prrp_solve_workspace_size(q.n, q.nrhs, &q.sws_bytes);
+      po[i].sws = take(q.sws_bytes);
+    }
+  }
+  const size_t off_abort = take(256);
+  const size_t off_iters = take((size_t)count * 4);
+  const size_t off_rels = take((size_t)count * 8);
+
+  // ---- work lists, step by step (host image, device offsets)
+  std::vector<char> host;
+  auto put = [&](const void* src, size_t bytes) {
+    const size_t o = align_up(host.size(), 256);
+    host.resize(o + bytes);
+    std::memcpy(host.data() + o, src, bytes);
+    return o;
+  };
+  std::vector<int> prevG(count, 0), prevBw(count, 0);
+  int64_t steps = 0;
+  for (int64_t i = 0; i < count; ++i) steps = std::max<int64_t>(steps, (n[i] + b[i] - 1) / b[i]);
+  struct SrrqrOpHost { SrrqrArgs a; size_t list_off; };
+  std::vector<SrrqrOpHost> sops;
+  for (int64_t s = 0; s < steps; ++s) {
+    const int par = (int)(s & 1);
+    // strong RRQR: classes of equal (bw, G)
+    std::vector<std::pair<std::pair<int, int>, int>> cls;   // ((bw, G), problem)
+    for (int64_t i = 0; i < count; ++i) {
+      const PlanProblem& q = P->p[i];
+      const int64_t k0 = s * q.b;
+      if (k0 >= q.n) continue;
+      const int64_t m = q.n - k0;
+      const int bw = (int)std::min<int64_t>(q.b, m);
+      cls.push_back({{bw, groups_for_rows(m, cap, rows_per_wg)}, (int)i});
+    }
+    std::stable_sort(cls.begin(), cls.end(),
+                     [](const auto& x, const auto& y) { return x.first < y.first; });
+    for (size_t c0 = 0; c0 < cls.size();) {
+      size_t c1 = c0;
+      while (c1 < cls.size() && cls[c1].first == cls[c0].first) ++c1;
+      const int bw = cls[c0].first.first, G = cls[c0].first.second;
+      std::vector<SrrqrProblem> list;
+      int64_t maxm = 0;
+      for (size_t c = c0; c < c1; ++c) {
+        const int i = cls[c].second;
+        PlanProblem& q = P->p[i];
+        const int64_t k0 = s * q.b, m = q.n - k0;
+        maxm = std::max(maxm, m);
+        SrrqrProblem sp;
+        std::memset(&sp, 0, sizeof sp);
+        sp.A = q.A; sp.lda = q.lda; sp.k0 = k0; sp.m = (int)m;
+        sp.Y = (m > bw) ? reinterpret_cast<double*>(po[i].y) : nullptr;   // offsets, fixed below
+        sp.ldy = q.b;
+        sp.sel_out = reinterpret_cast<int32_t*>(po[i].sel);
+        sp.slots = reinterpret_cast<uint64_t*>(po[i].slots + (size_t)par * q.set_words * 8);
+        sp.rounds_out = reinterpret_cast<int32_t*>(po[i].rounds + (size_t)par * 4);
+        if (s > 0) {
+          sp.clear_base = reinterpret_cast<uint64_t*>(po[i].slots + (size_t)(1 - par) * q.set_words * 8);
+          sp.clear_G = prevG[i];
+          sp.clear_bw = prevBw[i];
+          sp.clear_rounds = reinterpret_cast<int32_t*>(po[i].rounds + (size_t)(1 - par) * 4);
+        }
+        sp.stats = q.stats;
+        list.push_back(sp);
+        prevG[i] = G;
+        prevBw[i] = bw;
+      }
+      SrrqrOpHost so;
+      std::memset(&so.a, 0, sizeof so.a);
+      so.a.bw = bw;
+      so.a.ngroups = (int)list.size();
+      so.a.G = G;
+      so.a.rpw = (int)((maxm + G - 1) / G);
+      so.a.mode = 0;
+      so.a.tau_bits = tau_bits(tau);
+      so.a.report_rank = 1;
+      so.a.record_block_L = 1;
+      so.list_off = put(list.data(), list.size() * sizeof(SrrqrProblem));
+      PlanOp op{OP_SRRQR, so.list_off, (int)list.size(), bw, 0, 0, 0, (int)sops.size()};
+      sops.push_back(so);
+      P->ops.push_back(op);
+      c0 = c1;
+    }
+    // diagonal GEPP, moves, L21, U12, Schur: one launch each
+    std::vector<GeppArgs> gl;
+    std::vector<MoveArgs> ml;
+    std::vector<GemmArgs> l21, sch;
+    std::vector<TrsmArgs> tl;
+    int maxbw = 0;
+    int64_t maxout = 0, maxl21m = 0, maxnr = 0, maxschm = 0;
+    for (int64_t i = 0; i < count; ++i) {
+      PlanProblem& q = P->p[i];
+      const int64_t k0 = s * q.b;
+      if (k0 >= q.n) continue;
+      const int64_t m = q.n - k0;
+      const int bw = (int)std::min<int64_t>(q.b, m);
+      maxbw = std::max(maxbw, bw);
+      int32_t* mvp = reinterpret_cast<int32_t*>(po[i].mv);
+      int32_t* mv_dst = mvp;
+      int32_t* mv_src = mvp + 2 * kMaxB;
+      int32_t* n_moves = mvp + 4 * kMaxB;
+      double* Yp = reinterpret_cast<double*>(po[i].y);
+      double* PLp = reinterpret_cast<double*>(po[i].pl);
+      gl.push_back(GeppArgs{q.A, q.lda, k0, bw, (int)m, reinterpret_cast<int32_t*>(po[i].sel), PLp,
+                            mv_dst, mv_src, n_moves, q.stats});
+      ml.push_back(MoveArgs{q.A, q.lda, q.n, k0, bw, mv_dst, mv_src, n_moves, q.perm,
+                            (m > bw) ? Yp : nullptr, q.b});
+      maxout = std::max<int64_t>(maxout, q.n - bw);
+      if (m > bw) {
+        const int64_t nr = q.n - k0 - bw;
+        l21.push_back(GemmArgs{(int)(m - bw), bw, bw, Yp + (size_t)bw * q.b, q.b, PLp, bw,
+                               q.A + (k0 + bw) * q.lda + k0, q.lda, 1.0, 0.0, nullptr, nullptr,
+                               PRRP_FP64});
+        tl.push_back(TrsmArgs{q.A, q.lda, k0, bw, nr, &q.stats->max_abs_U, &q.stats->max_abs_W});
+        sch.push_back(GemmArgs{(int)(m - bw), (int)nr, bw, q.A + (k0 + bw) * q.lda + k0, q.lda,
+                               q.A + k0 * q.lda + k0 + bw, q.lda, q.A + (k0 + bw) * q.lda + k0 + bw,
+                               q.lda, -1.0, 1.0, &q.stats->max_abs_W, nullptr, schur});
+        maxl21m = std::max<int64_t>(maxl21m, m - bw);
+        maxnr = std::max<int64_t>(maxnr, nr);
+        maxschm = std::max<int64_t>(maxschm, m - bw);
+      }
+    }
+    P->ops.push_back(PlanOp{OP_GEPP, put(gl.data(), gl.size() * sizeof(GeppArgs)), (int)gl.size(),
+                            maxbw, 0, 0, 0, -1});
+    P->ops.push_back(PlanOp{OP_MOVES, put(ml.data(), ml.size() * sizeof(MoveArgs)), (int)ml.size(),
+                            maxbw, maxout, 0, 0, -1});
+    if (!l21.empty()) {
+      P->ops.push_back(PlanOp{OP_L21, put(l21.data(), l21.size() * sizeof(GemmArgs)),
+                              (int)l21.size(), maxbw, maxl21m, maxbw, PRRP_FP64, -1});
+      P->ops.push_back(PlanOp{OP_U12, put(tl.data(), tl.size() * sizeof(TrsmArgs)), (int)tl.size(),
+                              maxbw, maxnr, 0, 0, -1});
+      P->ops.push_back(PlanOp{OP_SCHUR, put(sch.data(), sch.size() * sizeof(GemmArgs)),
+                              (int)sch.size(), maxbw, maxschm, maxnr, schur, -1});
+    }
+  }
+
+  // ---- device memory: workspaces, then the work lists
+  const size_t lists_at = align_up(off, 256);
+  P->dbytes = lists_at + host.size();
+  if (hipMalloc(&P->dmem, P->dbytes) != hipSuccess) { plan_free(P); return -1002; }
+  char* base = P->dmem;
+  auto dptr = [&](size_t o) { return base + o; };
+  // relocate workspace offsets stored as pointers into device addresses
+  for (auto& so : sops) {
+    SrrqrProblem* lst = reinterpret_cast<SrrqrProblem*>(host.data() + so.list_off);
+    for (int g = 0; g < so.a.ngroups; ++g) {
+      SrrqrProblem& sp = lst[g];
+      if (sp.Y) sp.Y = reinterpret_cast<double*>(dptr(reinterpret_cast<size_t>(sp.Y)));
+      sp.sel_out = reinterpret_cast<int32_t*>(dptr(reinterpret_cast<size_t>(sp.sel_out)));
+      sp.slots = reinterpret_cast<uint64_t*>(dptr(reinterpret_cast<size_t>(sp.slots)));
+      sp.rounds_out = reinterpret_cast<int32_t*>(dptr(reinterpret_cast<size_t>(sp.rounds_out)));
+      if (sp.clear_base) {
+        sp.clear_base = reinterpret_cast<uint64_t*>(dptr(reinterpret_cast<size_t>(sp.clear_base)));
+        sp.clear_rounds = reinterpret_cast<const int32_t*>(
+            dptr(reinterpret_cast<size_t>(sp.clear_rounds)));
+      }
+    }
+    so.a.probs = reinterpret_cast<const SrrqrProblem*>(base + lists_at + so.list_off);
+    so.a.abort_flag = reinterpret_cast<uint32_t*>(base + off_abort);
+    P->srrqr_args.push_back(so.a);
+  }
+  for (PlanOp& o : P->ops) {
+    const size_t lo = o.off;
+    char* h = host.data() + lo;
+    auto fixp = [&](auto*& ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(
+                                      dptr(reinterpret_cast<size_t>(ptr))); };
+    if (o.kind == OP_GEPP) {
+      GeppArgs* g = reinterpret_cast<GeppArgs*>(h);
+      for (int k = 0; k < o.count; ++k) {
+        fixp(g[k].sel); fixp(g[k].PL); fixp(g[k].mv_dst); fixp(g[k].mv_src); fixp(g[k].n_moves);
+      }
+    } else if (o.kind == OP_MOVES) {
+      MoveArgs* m = reinterpret_cast<MoveArgs*>(h);
+      for (int k = 0; k < o.count; ++k) {
+        fixp(m[k].mv_dst); fixp(m[k].mv_src); fixp(m[k].n_moves);
+        if (m[k].Y) fixp(m[k].Y);
+      }
+    } else if (o.kind == OP_L21) {
+      GemmArgs* g = reinterpret_cast<GemmArgs*>(h);
+      for (int k = 0; k < o.count; ++k) { fixp(g[k].A); fixp(g[k].B); }
+    }
+    o.off = lists_at + lo;
+  }
+  P->slots_all = reinterpret_cast<uint64_t*>(base + slots_begin);
+  P->slots_words = (slots_end - slots_begin) / 8;
+  P->abort = reinterpret_cast<uint32_t*>(base + off_abort);
+  P->iters = reinterpret_cast<int32_t*>(base + off_iters);
+  P->rels = reinterpret_cast<double*>(base + off_rels);
+  if (refine) {
+    for (int64_t i = 0; i < count; ++i) P->p[i].sws = base + po[i].sws;
+  }
+  if (hipMemcpy(base + lists_at, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    plan_free(P);
+    return -1003;
+  }
+  if (refine) {
+    P->nforks = (int)std::min<int64_t>(4, count);
+    if (hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess) {
+      plan_free(P);
+      return -1004;
+    }
+    for (int f = 0; f < P->nforks; ++f) {
+      if (hipStreamCreateWithFlags(&P->forks[f], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&P->ev_join[f], hipEventDisableTiming) != hipSuccess) {
+        plan_free(P);
+        return -1004;
+      }
+    }
+  }
+  *plan_out = P;
+  return 0;
+}
+
+int prrp_batch_plan_run(void* plan, void* stream, int use_graph) {
+  if (!plan) return -1;
+  BatchPlan& P = *static_cast<BatchPlan*>(plan);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!use_graph) return herr(plan_enqueue(P, st));
+  if (!P.exec) {
+    // captured on a private stream (the caller's may be the legacy default
+    // stream, which cannot be captured); the graph is launched on the caller's
+    if (!P.cap) PRRP_TRY(hipStreamCreateWithFlags(&P.cap, hipStreamNonBlocking));
+    PRRP_TRY(hipStreamBeginCapture(P.cap, hipStreamCaptureModeRelaxed));
+    const hipError_t e = plan_enqueue(P, P.cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(P.cap, &g);
+    if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return herr(e); }
+    if (e2 != hipSuccess) return herr(e2);
+    P.graph = g;
+    PRRP_TRY(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+  }
+  return herr(hipGraphLaunch(P.exec, st));
+}
+
+int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels) {
+  if (!plan) return -1;
+  BatchPlan& P = *static_cast<BatchPlan*>(plan);
+  const size_t c = P.p.size();
+  if (iters) PRRP_TRY(hipMemcpy(iters, P.iters, c * 4, hipMemcpyDeviceToHost));
+  if (rels) PRRP_TRY(hipMemcpy(rels, P.rels, c * 8, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+int prrp_batch_plan_destroy(void* plan) {
+  plan_free(static_cast<BatchPlan*>(plan));
+  return 0;
+}
+
+int prrp_factor_batched(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
+                        const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
+                        int schur, void* stream) {
+  void* plan = nullptr;
+  int rc = prrp_batch_plan_create(count, A, n, lda, b, perm, stats, tau, schur, 64, nullptr,
+                                  nullptr, nullptr, nullptr, 0.0, 0, &plan);
+  if (rc) return rc;
+  rc = prrp_batch_plan_run(plan, stream, 0);
+  const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  prrp_batch_plan_destroy(plan);
+  if (rc) return rc;
+  return herr(e);
 }
 
 }  // extern "C"

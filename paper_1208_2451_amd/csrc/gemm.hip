@@ -55,7 +55,7 @@ template <> __device__ __forceinline__ unsigned short conv<unsigned short>(doubl
 
 // T: LDS/operand element type (double, float, bf16 as unsigned short).
 template <typename T, int BM, int BN>
-__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_body(const GemmArgs& g, int bx, int by) {
   constexpr int WI = BM / 32, WJ = BN / 32;    // 16x16 blocks per wave
   // bf16 needs K multiples of 32 per MFMA; stage 32-deep slabs for it
   constexpr int KS = (sizeof(T) == 2) ? 32 : BK;
@@ -67,8 +67,8 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * BM;
-  const int n0 = blockIdx.x * BN;
+  const int m0 = by * BM;
+  const int n0 = bx * BN;
   const int M = g.M, N = g.N, K = g.K;
 
   // global -> register staging: each thread holds KS*BM/256 A and KS*BN/256 B values
@@ -201,6 +201,34 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
       if (g.amax2) atomic_max_pos(g.amax2, mx);
     }
   }
+}
+
+template <typename T, int BM, int BN>
+__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
+  gemm_body<T, BM, BN>(g, blockIdx.x, blockIdx.y);
+}
+
+// Batched form: problem blockIdx.z of `list`; tiles outside a problem's C exit.
+template <typename T, int BM, int BN>
+__global__ __launch_bounds__(kGemmThreads) void gemm_batched_kernel(const GemmArgs* list) {
+  const GemmArgs g = list[blockIdx.z];
+  if ((int)blockIdx.y * BM >= g.M || (int)blockIdx.x * BN >= g.N) return;
+  gemm_body<T, BM, BN>(g, blockIdx.x, blockIdx.y);
+}
+
+hipError_t launch_gemm_batched(const GemmArgs* list, int count, int max_m, int max_n, int prec,
+                               hipStream_t stream) {
+  if (count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
+  dim3 grid((max_n + 63) / 64, (max_m + 63) / 64, count);
+  if (prec == PRRP_SCHUR_FP32)
+    hipLaunchKernelGGL((gemm_batched_kernel<float, 64, 64>), grid, dim3(kGemmThreads), 0, stream, list);
+  else if (prec == PRRP_SCHUR_BF16)
+    hipLaunchKernelGGL((gemm_batched_kernel<unsigned short, 64, 64>), grid, dim3(kGemmThreads), 0,
+                       stream, list);
+  else
+    hipLaunchKernelGGL((gemm_batched_kernel<double, 64, 64>), grid, dim3(kGemmThreads), 0, stream,
+                       list);
+  return hipGetLastError();
 }
 
 template <int BM, int BN>

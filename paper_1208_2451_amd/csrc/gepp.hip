@@ -42,7 +42,7 @@ struct LaneArr {
   }
 };
 
-__global__ __launch_bounds__(kGeppThreads) void gepp_kernel(GeppArgs a) {
+__device__ __forceinline__ void gepp_body(const GeppArgs& a) {
   extern __shared__ double sm[];
   const int bw = a.bw;
   const int ld = bw + 1;
@@ -288,6 +288,14 @@ __global__ __launch_bounds__(kGeppThreads) void gepp_kernel(GeppArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kGeppThreads) void gepp_kernel(GeppArgs a) { gepp_body(a); }
+
+// Batched form: problem blockIdx.x of `list`.
+__global__ __launch_bounds__(kGeppThreads) void gepp_batched_kernel(const GeppArgs* list) {
+  const GeppArgs a = list[blockIdx.x];
+  gepp_body(a);
+}
+
 size_t gepp_smem_bytes(int bw) {
   return sizeof(double) * (size_t)(bw * (bw + 1)) + sizeof(int) * (5 * kMaxB + 16);
 }
@@ -306,6 +314,21 @@ hipError_t launch_gepp(const GeppArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+hipError_t launch_gepp_batched(const GeppArgs* list, int count, int bw, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute((const void*)gepp_batched_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)gepp_smem_bytes(kMaxB));
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  hipLaunchKernelGGL(gepp_batched_kernel, dim3(count), dim3(kGeppThreads), gepp_smem_bytes(bw),
+                     stream, list);
+  return hipGetLastError();
+}
+
 // --------------------------------------------------------------- moves
 // Each workgroup moves a 32-column strip of every moved row through LDS;
 // columns [k0, k0 + bw) are skipped (overwritten by L11\U11 and L21).
@@ -315,13 +338,13 @@ constexpr int kMoveThreads = 256;
 constexpr int kStrip = 32;
 }
 
-__global__ __launch_bounds__(kMoveThreads) void moves_kernel(MoveArgs a) {
+__device__ __forceinline__ void moves_body(const MoveArgs& a, int bx, int nbx) {
   __shared__ double buf[2 * kMaxB][kStrip];
   __shared__ int64_t pbuf[2 * kMaxB];
   const int nm = *a.n_moves;
   const int tid = threadIdx.x;
   const int64_t outside = a.n - a.bw;          // columns outside the panel
-  const int64_t c0 = (int64_t)blockIdx.x * kStrip;
+  const int64_t c0 = (int64_t)bx * kStrip;
   const int cc = tid & (kStrip - 1);
   const int r8 = tid / kStrip;                 // 8 rows per pass
   int64_t col = c0 + cc;
@@ -340,13 +363,13 @@ __global__ __launch_bounds__(kMoveThreads) void moves_kernel(MoveArgs a) {
       if (t < nm) buf[t][cc] = v[u];
     }
   }
-  if (blockIdx.x == 0) {
+  if (bx == 0) {
     for (int t = tid; t < nm; t += kMoveThreads) pbuf[t] = a.perm[a.k0 + a.mv_src[t]];
   }
   __syncthreads();
   for (int t = r8; t < nm; t += kMoveThreads / kStrip)
     if (cvalid && a.mv_dst[t] != a.mv_src[t]) a.A[(a.k0 + a.mv_dst[t]) * a.lda + col] = buf[t][cc];
-  if (blockIdx.x == 0) {
+  if (bx == 0) {
     for (int t = tid; t < nm; t += kMoveThreads) a.perm[a.k0 + a.mv_dst[t]] = pbuf[t];
   }
   // Y rows: displaced rows (moves past the top block) carry their M columns;
@@ -354,8 +377,8 @@ __global__ __launch_bounds__(kMoveThreads) void moves_kernel(MoveArgs a) {
   if (a.Y) {
     const int nd = nm - a.bw;
     const int64_t total = (int64_t)nd * a.bw;
-    const int64_t stride = (int64_t)gridDim.x * kMoveThreads;
-    for (int64_t e0 = blockIdx.x * (int64_t)kMoveThreads + tid; e0 < total; e0 += 8 * stride) {
+    const int64_t stride = (int64_t)nbx * kMoveThreads;
+    for (int64_t e0 = bx * (int64_t)kMoveThreads + tid; e0 < total; e0 += 8 * stride) {
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -373,19 +396,33 @@ __global__ __launch_bounds__(kMoveThreads) void moves_kernel(MoveArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kMoveThreads) void moves_kernel(MoveArgs a) {
+  moves_body(a, blockIdx.x, gridDim.x);
+}
+
+// Batched form: problem blockIdx.y of `list`, strips blockIdx.x.
+__global__ __launch_bounds__(kMoveThreads) void moves_batched_kernel(const MoveArgs* list) {
+  const MoveArgs a = list[blockIdx.y];
+  moves_body(a, blockIdx.x, gridDim.x);
+}
+
 // U12 = L11^-1 A12: 32 columns per workgroup, 8 lanes per column, lane l8 of a
 // column holding rows l8, l8 + 8, ...; L11 (strict lower, packed by rows) in LDS.
 namespace {
 constexpr int kTrsmCols = 32;
 }
 
-__global__ __launch_bounds__(256) void trsm_u12_kernel(double* A, int64_t lda, int64_t k0, int bw,
-                                                       int64_t nr, double* amax1, double* amax2) {
+__device__ __forceinline__ void trsm_u12_body(const TrsmArgs& t, int bx) {
   extern __shared__ double Lp[];            // L(i,k), k < i, at i(i-1)/2 + k
+  double* A = t.A;
+  const int64_t lda = t.lda, k0 = t.k0, nr = t.nr;
+  const int bw = t.bw;
+  double* amax1 = t.amax1;
+  double* amax2 = t.amax2;
   const int tid = threadIdx.x;
   const int l8 = tid & 7;
   const int lane = tid & 63;
-  const int64_t c = (int64_t)blockIdx.x * kTrsmCols + (tid >> 3);
+  const int64_t c = (int64_t)bx * kTrsmCols + (tid >> 3);
   {
     // rows i = (tid >> 5) + 8u, columns k = (tid & 31) + 32w; loads first
     double v[16][4];
@@ -454,6 +491,16 @@ __global__ __launch_bounds__(256) void trsm_u12_kernel(double* A, int64_t lda, i
   }
 }
 
+__global__ __launch_bounds__(256) void trsm_u12_kernel(TrsmArgs t) { trsm_u12_body(t, blockIdx.x); }
+
+// Batched form: problem blockIdx.y of `list`; column blocks past a problem's
+// columns exit.
+__global__ __launch_bounds__(256) void trsm_u12_batched_kernel(const TrsmArgs* list) {
+  const TrsmArgs t = list[blockIdx.y];
+  if ((int64_t)blockIdx.x * kTrsmCols >= t.nr) return;
+  trsm_u12_body(t, blockIdx.x);
+}
+
 hipError_t launch_trsm_u12(double* A, int64_t lda, int64_t k0, int bw, int64_t nr, double* amax1,
                            double* amax2, hipStream_t stream) {
   if (nr <= 0) return hipSuccess;
@@ -466,9 +513,26 @@ hipError_t launch_trsm_u12(double* A, int64_t lda, int64_t k0, int bw, int64_t n
     attr_done = true;
   }
   const int64_t grid = (nr + kTrsmCols - 1) / kTrsmCols;
+  TrsmArgs t{A, lda, k0, bw, nr, amax1, amax2};
   hipLaunchKernelGGL(trsm_u12_kernel, dim3((unsigned)grid), dim3(256),
-                     sizeof(double) * (size_t)(bw * (bw - 1) / 2 + 1), stream, A, lda, k0, bw, nr,
-                     amax1, amax2);
+                     sizeof(double) * (size_t)(bw * (bw - 1) / 2 + 1), stream, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_u12_batched(const TrsmArgs* list, int count, int bw, int64_t max_nr,
+                                   hipStream_t stream) {
+  if (count <= 0 || max_nr <= 0) return hipSuccess;
+  static bool attr_done = false;
+  const size_t smem = sizeof(double) * (size_t)(kMaxB * (kMaxB - 1) / 2 + 1);
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute((const void*)trsm_u12_batched_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  const int64_t grid = (max_nr + kTrsmCols - 1) / kTrsmCols;
+  hipLaunchKernelGGL(trsm_u12_batched_kernel, dim3((unsigned)grid, (unsigned)count), dim3(256),
+                     sizeof(double) * (size_t)(bw * (bw - 1) / 2 + 1), stream, list);
   return hipGetLastError();
 }
 
@@ -476,6 +540,15 @@ hipError_t launch_moves(const MoveArgs& a, hipStream_t stream) {
   const int64_t outside = a.n - a.bw;
   const int64_t grid = std::max<int64_t>(1, (outside + kStrip - 1) / kStrip);
   hipLaunchKernelGGL(moves_kernel, dim3((unsigned)grid), dim3(kMoveThreads), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_moves_batched(const MoveArgs* list, int count, int64_t max_outside,
+                                hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  const int64_t grid = std::max<int64_t>(1, (max_outside + kStrip - 1) / kStrip);
+  hipLaunchKernelGGL(moves_batched_kernel, dim3((unsigned)grid, (unsigned)count),
+                     dim3(kMoveThreads), 0, stream, list);
   return hipGetLastError();
 }
 

@@ -12,6 +12,25 @@ constexpr int kPostW = 2 + 128;   // words per posted candidate: key, slot, row
 constexpr int kMaxGroups = 256;   // tiles per srrqr launch
 
 // ------------------------------------------------------------ strong RRQR
+// One problem of a batched launch (group g of the grid is problem g): its
+// panel, outputs and slot sets.  Panel rows are the m rows below k0.
+struct SrrqrProblem {
+  const double* A;
+  int64_t lda;
+  int64_t k0;
+  int m;
+  int pad0;
+  double* Y;                  // nullable
+  int64_t ldy;
+  int32_t* sel_out;           // [kMaxB]
+  uint64_t* slots;            // this launch's slot set of the problem
+  int32_t* rounds_out;        // [1]
+  uint64_t* clear_base;       // the problem's previous slot set (nullable)
+  int clear_G, clear_bw;
+  const int32_t* clear_rounds;
+  prrp_stats* stats;
+};
+
 struct SrrqrArgs {
   const double* A;
   int64_t lda;
@@ -40,6 +59,7 @@ struct SrrqrArgs {
   const int32_t* clear_rounds;
   prrp_stats* stats;
   uint32_t* abort_flag;
+  const SrrqrProblem* probs;  // nullable: batched launch, one problem per group
 };
 hipError_t launch_srrqr(const SrrqrArgs& a, hipStream_t stream);
 size_t srrqr_smem_bytes(int bw);
@@ -79,6 +99,25 @@ struct MoveArgs {
 };
 hipError_t launch_moves(const MoveArgs& a, hipStream_t stream);
 
+// U12 = L11^-1 A12 of the panel at k0 (nr columns right of the panel).
+struct TrsmArgs {
+  double* A;
+  int64_t lda;
+  int64_t k0;
+  int bw;
+  int64_t nr;
+  double* amax1;              // nullable: max |U12| recorded here
+  double* amax2;              // nullable: and here
+};
+
+// Batched forms: one problem per entry of a device-resident list; the grid
+// covers the largest problem and surplus workgroups exit.
+hipError_t launch_gepp_batched(const GeppArgs* list, int count, int bw, hipStream_t stream);
+hipError_t launch_moves_batched(const MoveArgs* list, int count, int64_t max_outside,
+                                hipStream_t stream);
+hipError_t launch_trsm_u12_batched(const TrsmArgs* list, int count, int bw, int64_t max_nr,
+                                   hipStream_t stream);
+
 // -------------------------------------------------------------- GEMMs
 // C = alpha * A * B + beta * C, row-major, FP64 operands; the Schur variants
 // round A and B to `prec` and accumulate in FP32 (prec != PRRP_FP64).
@@ -94,6 +133,8 @@ struct GemmArgs {
   int prec;
 };
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream);
+hipError_t launch_gemm_batched(const GemmArgs* list, int count, int max_m, int max_n, int prec,
+                               hipStream_t stream);
 
 // -------------------------------------------------------------- misc
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
@@ -105,18 +146,30 @@ hipError_t launch_init_factor(const double* A, int64_t n, int64_t lda, int64_t* 
 // X = B[perm]; fills Y (nullable) with the sentinel and zeroes tickets[0..1].
 hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm, double* X,
                               int64_t ldx, int64_t n, int64_t nrhs, double* Y, int64_t ldy,
-                              uint32_t* tickets, hipStream_t s);
+                              uint32_t* tickets, const uint32_t* skip, hipStream_t s);
 // Blocked triangular solve; Yout must hold the sentinel on entry and *ticket
 // must be 0.  Fill (nullable) receives the sentinel, block by block, once a
 // block's rows of Bin have been consumed.
 hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, const double* Bin,
                                int64_t ldb, double* Yout, int64_t ld, int64_t nrhs, int lower,
-                               uint32_t* ticket, double* Fill, int64_t ldf, hipStream_t s);
+                               uint32_t* ticket, double* Fill, int64_t ldf, const uint32_t* skip,
+                               hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double* X, int64_t ldx,
                            const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
-                           hipStream_t s);
+                           const uint32_t* skip, hipStream_t s);
 hipError_t launch_axpy_maxrel(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t n,
-                              int64_t nrhs, double* out2, hipStream_t s);
+                              int64_t nrhs, double* out2, const uint32_t* skip, hipStream_t s);
+
+// Device-resident state of a refinement loop (see ir_check_kernel).
+struct IrState {
+  uint32_t done;
+  uint32_t iter;
+  double prev;
+};
+hipError_t launch_ir_init(IrState* st, double* mx, int64_t nrhs, int32_t* iters_out,
+                          double* rel_out, hipStream_t s);
+hipError_t launch_ir_check(IrState* st, double* mx, int64_t nrhs, double tol, int max_iter,
+                           int32_t* iters_out, double* rel_out, hipStream_t s);
 hipError_t launch_build_lists(const int32_t* child_sel, int nchild, int bw, int32_t* lists,
                               int32_t* promoted_out, int npairs, int flat_tile_start,
                               int flat_tile_len, hipStream_t s);

@@ -26,7 +26,8 @@ constexpr int RC = 8;    // right-hand sides per pass
 // first solve's output Y with the sentinel.
 __global__ void gather_rows_kernel(const double* B, int64_t ldb, const int64_t* perm, double* X,
                                    int64_t ldx, int64_t n, int64_t nrhs, double* Y, int64_t ldy,
-                                   uint32_t* tickets) {
+                                   uint32_t* tickets, const uint32_t* skip) {
+  if (skip && *skip) return;
   const int64_t total = n * nrhs;
   if (blockIdx.x == 0 && threadIdx.x < 2 && tickets) tickets[threadIdx.x] = 0u;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -39,11 +40,11 @@ __global__ void gather_rows_kernel(const double* B, int64_t ldb, const int64_t* 
 
 hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm, double* X,
                               int64_t ldx, int64_t n, int64_t nrhs, double* Y, int64_t ldy,
-                              uint32_t* tickets, hipStream_t s) {
+                              uint32_t* tickets, const uint32_t* skip, hipStream_t s) {
   int64_t blocks = (n * nrhs + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, B, ldb, perm, X,
-                     ldx, n, nrhs, Y, ldy, tickets);
+                     ldx, n, nrhs, Y, ldy, tickets, skip);
   return hipGetLastError();
 }
 
@@ -51,7 +52,9 @@ template <bool LOWER, int RCT>
 __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, int64_t lda,
                                                    const double* Bin, int64_t ldb, double* Yout,
                                                    int64_t ld, int64_t nrhs, uint32_t* ticket,
-                                                   double* Fill, int64_t ldf) {
+                                                   double* Fill, int64_t ldf,
+                                                   const uint32_t* skip) {
+  if (skip && *skip) return;
   // Yout starts out holding the sentinel; every solution value is written
   // exactly once, so dependent blocks poll the values they need.
   __shared__ double D[NB][NB + 1];
@@ -181,11 +184,12 @@ __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, 
 
 hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, const double* Bin,
                                int64_t ldb, double* Yout, int64_t ld, int64_t nrhs, int lower,
-                               uint32_t* ticket, double* Fill, int64_t ldf, hipStream_t s) {
+                               uint32_t* ticket, double* Fill, int64_t ldf, const uint32_t* skip,
+                               hipStream_t s) {
   const int nb = (int)((n + NB - 1) / NB);
 #define PRRP_TRSV(LO, R)                                                                       \
   hipLaunchKernelGGL((trsv_kernel<LO, R>), dim3(nb), dim3(256), 0, s, LU, n, lda, Bin, ldb, Yout, \
-                     ld, nrhs, ticket, Fill, ldf)
+                     ld, nrhs, ticket, Fill, ldf, skip)
   if (nrhs == 1) {
     if (lower) PRRP_TRSV(true, 1); else PRRP_TRSV(false, 1);
   } else {
@@ -207,7 +211,8 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
 __global__ __launch_bounds__(256) void residual_kernel(const double* A, int64_t n, int64_t lda,
                                                        const double* X, int64_t ldx, const double* B,
                                                        int64_t ldb, double* R, int64_t ldr,
-                                                       int64_t nrhs) {
+                                                       int64_t nrhs, const uint32_t* skip) {
+  if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
@@ -255,10 +260,10 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* A, int64_t 
 
 hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double* X, int64_t ldx,
                            const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
-                           hipStream_t s) {
+                           const uint32_t* skip, hipStream_t s) {
   const int64_t blocks = (n + 3) / 4;
   hipLaunchKernelGGL(residual_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, X, ldx,
-                     B, ldb, R, ldr, nrhs);
+                     B, ldb, R, ldr, nrhs, skip);
   return hipGetLastError();
 }
 
@@ -266,7 +271,8 @@ hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double
 // One thread per row; maxima reduced per wave before the device-scope max.
 __global__ __launch_bounds__(256) void axpy_maxrel_kernel(double* X, int64_t ldx, const double* D,
                                                           int64_t ldd, int64_t n, int64_t nrhs,
-                                                          double* out) {
+                                                          double* out, const uint32_t* skip) {
+  if (skip && *skip) return;
   const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
   for (int64_t r = 0; r < nrhs; ++r) {
     double dm = 0.0, xm = 0.0;
@@ -290,10 +296,62 @@ __global__ __launch_bounds__(256) void axpy_maxrel_kernel(double* X, int64_t ldx
 }
 
 hipError_t launch_axpy_maxrel(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t n,
-                              int64_t nrhs, double* out, hipStream_t s) {
+                              int64_t nrhs, double* out, const uint32_t* skip, hipStream_t s) {
   const int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(axpy_maxrel_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, ldx, D, ldd,
-                     n, nrhs, out);
+                     n, nrhs, out, skip);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------- device-side refinement loop
+// State of a refinement run kept on the device so that the whole loop can be
+// enqueued (or captured in a graph) without host round trips: the stopping
+// test runs in ir_check_kernel and later iterations' kernels see `done` and
+// return at once.
+__global__ void ir_init_kernel(IrState* st, double* mx, int64_t nrhs, int32_t* iters_out,
+                               double* rel_out) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    st->done = 0u;
+    st->iter = 0u;
+    st->prev = __longlong_as_double(0x7FF0000000000000ll);   // +inf
+    if (iters_out) *iters_out = 0;
+    if (rel_out) *rel_out = 0.0;
+  }
+  for (int64_t i = t; i < 2 * nrhs; i += blockDim.x) mx[i] = 0.0;
+}
+
+// Same stopping test as the host-driven loop: stop when the correction is at
+// most tol times the solution (per right-hand side, worst case), or when it
+// no longer halves, or after max_iter corrections.
+__global__ void ir_check_kernel(IrState* st, double* mx, int64_t nrhs, double tol, int max_iter,
+                                int32_t* iters_out, double* rel_out) {
+  if (threadIdx.x != 0 || st->done) return;
+  double rel = 0.0;
+  for (int64_t r = 0; r < nrhs; ++r) {
+    const double xm = mx[2 * r + 1] > 0.0 ? mx[2 * r + 1] : 1.0;
+    rel = fmax(rel, mx[2 * r] / xm);
+    mx[2 * r] = 0.0;
+    mx[2 * r + 1] = 0.0;
+  }
+  const unsigned it = st->iter + 1u;
+  st->iter = it;
+  if (!(rel > tol) || rel > 0.5 * st->prev || (int)it >= max_iter) st->done = 1u;
+  st->prev = rel;
+  if (iters_out) *iters_out = (int32_t)it;
+  if (rel_out) *rel_out = rel;
+}
+
+hipError_t launch_ir_init(IrState* st, double* mx, int64_t nrhs, int32_t* iters_out,
+                          double* rel_out, hipStream_t s) {
+  hipLaunchKernelGGL(ir_init_kernel, dim3(1), dim3(64), 0, s, st, mx, nrhs, iters_out, rel_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_check(IrState* st, double* mx, int64_t nrhs, double tol, int max_iter,
+                           int32_t* iters_out, double* rel_out, hipStream_t s) {
+  hipLaunchKernelGGL(ir_check_kernel, dim3(1), dim3(64), 0, s, st, mx, nrhs, tol, max_iter,
+                     iters_out, rel_out);
   return hipGetLastError();
 }
 

@@ -92,15 +92,51 @@ void srrqr_kernel(SrrqrArgs a) {
   const int rg = tid >> 3;
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  const int tlen = a.tile_len[g];
-  const int tstart = a.tile_start[g];
+  // the tile (or, for a batch, the problem) of this group
+  const double* pA = a.A;
+  int64_t plda = a.lda, pk0 = a.k0;
+  double* pY = a.Y;
+  int64_t pldy = a.ldy;
+  prrp_stats* pst = a.stats;
+  int32_t* psel = a.sel_out ? a.sel_out + (size_t)g * kMaxB : nullptr;
+  int32_t* prounds = a.rounds_out ? a.rounds_out + g : nullptr;
+  int tlen, tstart;
+  uint64_t* slots;
+  if (a.probs != nullptr) {
+    const SrrqrProblem& P = a.probs[g];
+    pA = P.A; plda = P.lda; pk0 = P.k0;
+    pY = P.Y; pldy = P.ldy;
+    pst = P.stats;
+    psel = P.sel_out;
+    prounds = P.rounds_out;
+    tlen = P.m;
+    tstart = 0;
+    slots = P.slots;
+  } else {
+    tlen = a.tile_len[g];
+    tstart = a.tile_start[g];
+    slots = a.slots + (size_t)g * a.group_stride;
+  }
   const int row0 = w * a.rpw;
   const int nloc = max(0, min(a.rpw, tlen - row0));
-  uint64_t* slots = a.slots + (size_t)g * a.group_stride;
   const size_t round_stride = (size_t)G * kPostW;
 
   // ---- restore the sentinels of the slot set used by the previous launch
-  if (a.clear_base != nullptr) {
+  // (a batch: each problem's own previous set, by that problem's workgroups)
+  if (a.probs != nullptr) {
+    const SrrqrProblem& P = a.probs[g];
+    if (P.clear_base != nullptr) {
+      const int nthr = G * kThreads;
+      const int gt = w * kThreads + tid;
+      const int per_post = 2 + P.clear_bw;
+      const size_t total = (size_t)(*P.clear_rounds) * P.clear_G * per_post;
+      for (size_t e = gt; e < total; e += nthr) {
+        const size_t post = e / per_post;
+        const int wd = (int)(e - post * per_post);
+        P.clear_base[post * kPostW + wd] = kKeySent;
+      }
+    }
+  } else if (a.clear_base != nullptr) {
     const int nthr = gridDim.x * kThreads;
     const int gt = blockIdx.x * kThreads + tid;
     const int per_post = 2 + a.clear_bw;
@@ -128,7 +164,7 @@ void srrqr_kernel(SrrqrArgs a) {
     chosen[q] = false;
     int64_t prow_idx = 0;
     if (live[q]) prow_idx = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + tpos[q];
-    const double* src = a.A + (a.k0 + prow_idx) * a.lda + a.k0;
+    const double* src = pA + (pk0 + prow_idx) * plda + pk0;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       const int c = l8 + 8 * k;
@@ -234,13 +270,13 @@ void srrqr_kernel(SrrqrArgs a) {
         gkey = wave_max_key(kv);
       }
       if (gkey == 0 && !wbad) {      // fewer rows than columns: not a valid tile
-        if (tid == 0) set_info(a.stats, -2);
+        if (tid == 0) set_info(pst, -2);
         wbad = 1;
       }
-      if (key_nonfinite(gkey) && tid == 0) set_info(a.stats, -1);
+      if (key_nonfinite(gkey) && tid == 0) set_info(pst, -1);
       if ((gkey >> kDropBits) == 0 && tid == 0) {     // exactly zero residual
         S.flags[1] = 1;
-        if (a.report_rank) set_info(a.stats, (int32_t)(a.k0 + s + 1));
+        if (a.report_rank) set_info(pst, (int32_t)(pk0 + s + 1));
       }
       p = (int)key_index(gkey);
     } else {
@@ -281,7 +317,7 @@ void srrqr_kernel(SrrqrArgs a) {
 
   if (S.flags[0]) {
     if (tid == 0) {
-      set_info(a.stats, -2);
+      set_info(pst, -2);
       st_dev_u32(a.abort_flag, 1u);
     }
     return;
@@ -290,7 +326,7 @@ void srrqr_kernel(SrrqrArgs a) {
   int rounds_used = bw;
   int swaps = 0;
   const bool rank_def = S.flags[1] != 0;
-  const bool need_m = (a.mode == 1) ? (a.Y != nullptr) : true;
+  const bool need_m = (a.mode == 1) ? (pY != nullptr) : true;
   double mmax_local = 0.0;
 
   if (need_m && !rank_def && tlen > bw) {
@@ -391,7 +427,7 @@ void srrqr_kernel(SrrqrArgs a) {
         const bool violate = gkey != 0 && (gkey >> kDropBits) > a.tau_bits;
         if (!violate) break;
         if (e >= kMaxExchange) {
-          if (tid == 0) set_info(a.stats, -3);
+          if (tid == 0) set_info(pst, -3);
           break;
         }
         const int pj = (int)key_index(gkey);
@@ -458,7 +494,7 @@ void srrqr_kernel(SrrqrArgs a) {
         __syncthreads();
       }
       if (S.flags[0]) {
-        if (tid == 0) { set_info(a.stats, -2); st_dev_u32(a.abort_flag, 1u); }
+        if (tid == 0) { set_info(pst, -2); st_dev_u32(a.abort_flag, 1u); }
         return;
       }
     }
@@ -473,21 +509,21 @@ void srrqr_kernel(SrrqrArgs a) {
           const int c = l8 + 8 * k;
           if (c < bw) {
             mmax_local = fmax(mmax_local, fabs(x[q][k]));
-            if (a.Y) a.Y[pr * a.ldy + c] = x[q][k];
+            if (pY) pY[pr * pldy + c] = x[q][k];
           }
         }
       }
     }
   }
 
-  if (rank_def && a.Y) {
+  if (rank_def && pY) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       if (live[q] && !chosen[q]) {
         const int64_t pr = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + tpos[q];
 #pragma unroll
         for (int k = 0; k < CPT; ++k)
-          if (l8 + 8 * k < bw) a.Y[pr * a.ldy + l8 + 8 * k] = 0.0;
+          if (l8 + 8 * k < bw) pY[pr * pldy + l8 + 8 * k] = 0.0;
       }
     }
   }
@@ -495,17 +531,17 @@ void srrqr_kernel(SrrqrArgs a) {
   // ------------------------------------------------------ selection, stats
   if (w == 0 && tid < bw) {
     const int sp = S.selpos[tid];
-    a.sel_out[g * kMaxB + tid] = a.row_list ? a.row_list[tstart + sp] : tstart + sp;
+    psel[tid] = a.row_list ? a.row_list[tstart + sp] : tstart + sp;
   }
-  if (a.stats) {
+  if (pst) {
     double m = mmax_local;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if (lane == 0 && m > 0.0 && a.record_block_L) atomic_max_pos(&a.stats->max_block_L, m);
+    if (lane == 0 && m > 0.0 && a.record_block_L) atomic_max_pos(&pst->max_block_L, m);
     if (w == 0 && tid == 0 && swaps > 0)
-      __hip_atomic_fetch_add(&a.stats->swaps, (int64_t)swaps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&pst->swaps, (int64_t)swaps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (w == 0 && tid == 0) a.rounds_out[g] = rounds_used;
+  if (w == 0 && tid == 0) *prounds = rounds_used;
 }
 
 // ------------------------------------------------------------- dispatch

@@ -94,3 +94,35 @@ def test_refine_argument_errors(L):
     rel = ctypes.c_double(0)
     assert L.prrp_refine(1, 1, 8, 8, 1, 1, 1, 1, 1, -1.0, 5, ctypes.byref(it), ctypes.byref(rel),
                          1, 1 << 30, None) == -10
+
+
+def test_refine_async_argument_errors(L):
+    assert L.prrp_refine_async(1, 1, 8, 8, 1, 1, 1, 1, 1, -1.0, 5, None, None, 1, 1 << 30,
+                               None) == -10
+    assert L.prrp_refine_async(1, 1, 8, 8, 1, 1, 1, 1, 1, 1e-14, 5000, None, None, 1, 1 << 30,
+                               None) == -11
+    assert L.prrp_refine_async(1, 1, 8, 8, 1, 1, 1, 1, 1, 1e-14, 5, None, None, 1, 16,
+                               None) == -15
+
+
+def test_batch_plan_argument_errors(L):
+    one_p = (ctypes.c_void_p * 1)(1)
+    n8 = (ctypes.c_int64 * 1)(8)
+    b2 = (ctypes.c_int * 1)(2)
+    h = ctypes.c_void_p(0)
+    args = lambda **kw: dict(dict(count=1, A=one_p, n=n8, lda=n8, b=b2, perm=one_p, stats=1,  # noqa: E731
+                                  tau=2.0, schur=0, rpw=64), **kw)
+
+    def call(**kw):
+        a = args(**kw)
+        return L.prrp_batch_plan_create(a["count"], a["A"], a["n"], a["lda"], a["b"], a["perm"],
+                                        a["stats"], a["tau"], a["schur"], a["rpw"], None, None,
+                                        None, None, 0.0, 0, ctypes.byref(h))
+    assert call(count=0) == -1
+    assert call(tau=1.0) == -8
+    assert call(schur=3) == -9
+    assert call(rpw=96) == -10
+    assert call(b=(ctypes.c_int * 1)(9)) == -5       # b > n
+    assert call(lda=(ctypes.c_int64 * 1)(4)) == -4   # lda < n
+    assert L.prrp_batch_plan_run(None, None, 0) == -1
+    assert L.prrp_batch_plan_destroy(None) == 0
