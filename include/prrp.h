@@ -143,28 +143,41 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
  * n[i] x n[i], row-major, lda[i]), panel width b[i], perm[i] (device, n[i]
  * int64), stats + i (device array of count records), tau, the Schur
  * precision and the rows per panel workgroup (64 or 128: fewer, fuller
- * workgroups per strong RRQR step).  With A0 non-NULL each system is also
- * refined after its factorization (as prrp_refine_async, tolerance tol, at
- * most max_iter corrections): A0[i] the original matrix (lda[i]), B[i] and
- * X[i] n[i] x nrhs[i] row-major.  The plan allocates and owns its device
- * memory (work lists and per-problem workspaces) at creation, which returns
- * 0 or -k for an invalid argument k, -1002 when device memory runs out.
- * Running a plan enqueues, on `stream`, one launch per kernel per panel
- * step over all problems still active, results equal to factoring each
- * system alone with prrp_factor_mixed; with use_graph the sequence is
- * captured into a HIP graph on the first run and replayed afterwards.  Plans
- * hold no other state between runs; runs of one plan must not overlap. */
+ * workgroups per strong RRQR step; the results are the same).  With A0
+ * non-NULL each system is also refined after its factorization (as
+ * prrp_refine_async, tolerance tol, at most max_iter corrections): A0[i] the
+ * original matrix (lda[i]), B[i] and X[i] n[i] x nrhs[i] row-major.
+ *
+ * All device memory of the plan (work lists and per-problem workspaces) is
+ * the caller's workspace of at least prrp_batch_plan_workspace_size bytes
+ * (nrhs NULL when there is no refinement), which must stay allocated and
+ * untouched until the plan is destroyed.  Creation uploads the work lists
+ * with an asynchronous copy on `stream` and returns 0, or -k for an invalid
+ * argument k (-17 no workspace, -18 workspace too small).
+ *
+ * Running a plan enqueues on `stream` one launch per kernel per panel step
+ * over all problems still active; each system ends with exactly the factors,
+ * permutation and statistics prrp_factor_mixed gives it alone.  With
+ * use_graph the sequence is captured into a HIP graph on the first run and
+ * replayed afterwards.  Runs of one plan must not overlap; plans that run
+ * concurrently share four fork streams for their refinements. */
+int prrp_batch_plan_workspace_size(int64_t count, const int64_t* n, const int* b,
+                                   const int64_t* nrhs, int rows_per_wg, size_t* bytes);
 int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
                            const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
                            int schur, int rows_per_wg, const double* const* A0,
                            const double* const* B, double* const* X, const int64_t* nrhs,
-                           double tol, int max_iter, void** plan);
+                           double tol, int max_iter, void* workspace, size_t ws_bytes,
+                           void* stream, void** plan);
 int prrp_batch_plan_run(void* plan, void* stream, int use_graph);
 /* Copies the refinement iteration counts and last ratios (count each) to the
- * host (synchronous; NULL skips). */
-int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels);
+ * host with copies on `stream`, and waits for that stream (NULL skips). */
+int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels, void* stream);
+/* Releases the plan's host state (graph, events); the workspace is the
+ * caller's.  Work the plan enqueued must have completed. */
 int prrp_batch_plan_destroy(void* plan);
-/* One-shot batched factorization: create a plan, run it, wait, destroy it. */
+/* One-shot batched factorization: allocates a workspace, creates, runs and
+ * destroys a plan, and waits for the stream (synchronous, allocating). */
 int prrp_factor_batched(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
                         const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
                         int schur, void* stream);

@@ -228,11 +228,17 @@ class BatchPlan:
             pX = arr(ctypes.c_void_p, [x.data_ptr() for x in self.solutions])
             pnr = arr(ctypes.c_int64, [r.shape[1] for r in self.rhs])
             self._keep += [pA0, pB, pX, pnr]
+        need = ctypes.c_size_t(0)
+        _lib.check(_lib.lib().prrp_batch_plan_workspace_size(count, pn, pb, pnr, int(rows_per_wg),
+                                                             ctypes.byref(need)),
+                   "prrp_batch_plan_workspace_size")
+        self.workspace = _alloc(need.value, dev)
         handle = ctypes.c_void_p(0)
         code = _lib.lib().prrp_batch_plan_create(
             count, pA, pn, plda, pb, pperm, self.stats_raw.data_ptr(), float(tau),
             _lib.PRECISIONS[precision], int(rows_per_wg), pA0, pB, pX, pnr, float(tol),
-            int(max_iter), ctypes.byref(handle))
+            int(max_iter), self.workspace.data_ptr(), self.workspace.numel(), _stream_ptr(),
+            ctypes.byref(handle))
         _lib.check(code, "prrp_batch_plan_create")
         self._h = handle
 
@@ -253,14 +259,18 @@ class BatchPlan:
         count = len(self.mats)
         it = (ctypes.c_int32 * count)()
         rel = (ctypes.c_double * count)()
-        _lib.check(_lib.lib().prrp_batch_plan_results(self._h, it, rel), "prrp_batch_plan_results")
+        _lib.check(_lib.lib().prrp_batch_plan_results(self._h, it, rel, _stream_ptr()),
+                   "prrp_batch_plan_results")
         return list(it), list(rel)
 
-    def close(self):
-        """Waits for the device, then frees the plan's memory."""
+    def close(self, synchronize: bool = True):
+        """Releases the plan (its workspace is a torch tensor freed with this
+        object).  Waits for the device first unless the caller knows that the
+        plan's work has completed (synchronize=False)."""
         from . import _lib
         if getattr(self, "_h", None) is not None and self._h.value:
-            _torch().cuda.synchronize()
+            if synchronize:
+                _torch().cuda.synchronize()
             _lib.lib().prrp_batch_plan_destroy(self._h)
             self._h = None
 

@@ -48,10 +48,12 @@ _SIGS = {
                            ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _sz, _vp]),
     "prrp_refine_async": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _dbl, _i32,
                                  _vp, _vp, _vp, _sz, _vp]),
+    "prrp_batch_plan_workspace_size": (_i32, [_i64, _vp, _vp, _vp, _i32, ctypes.POINTER(_sz)]),
     "prrp_batch_plan_create": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, _i32,
-                                      _vp, _vp, _vp, _vp, _dbl, _i32, ctypes.POINTER(_vp)]),
+                                      _vp, _vp, _vp, _vp, _dbl, _i32, _vp, _sz, _vp,
+                                      ctypes.POINTER(_vp)]),
     "prrp_batch_plan_run": (_i32, [_vp, _vp, _i32]),
-    "prrp_batch_plan_results": (_i32, [_vp, _vp, _vp]),
+    "prrp_batch_plan_results": (_i32, [_vp, _vp, _vp, _vp]),
     "prrp_batch_plan_destroy": (_i32, [_vp]),
     "prrp_factor_batched": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, _vp]),
     "prrp_gemm": (_i32, [_i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64, _dbl, _vp, _i64, _i32, _vp]),

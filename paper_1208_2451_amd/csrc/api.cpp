@@ -833,11 +833,10 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
 // covers every problem still active (one group of workgroups per problem,
 // problems of equal panel width and workgroup count sharing a launch), and
 // the diagonal GEPP, row moves, L21 product, U12 solve and Schur update of
-// the step are one launch each over all active problems.  The plan owns its
-// device memory (work lists and per-problem workspaces, allocated at
-// creation).  Its launch sequence can be captured once into a HIP graph and
-// replayed; optional per-problem refinement runs on fork streams inside the
-// same sequence.
+// the step are one launch each over all active problems.  Its device memory
+// (work lists and per-problem workspaces) is a caller-provided workspace.
+// The launch sequence can be captured once into a HIP graph and replayed;
+// optional per-problem refinement runs on fork streams inside the sequence.
 // ==========================================================================
 namespace {
 
@@ -847,15 +846,9 @@ struct PlanProblem {
   int b;
   int64_t* perm;
   prrp_stats* stats;
-  // plan-owned workspace
-  uint64_t* slots[2];
-  int32_t* rounds;        // [2]
-  int32_t* sel;           // [kMaxB]
-  double* Y;              // n x b
-  double* PL;             // b x b
-  int32_t* mv;            // 4 kMaxB + 4
   int Gmax;
   size_t set_words;
+  size_t off_slots, off_rounds, off_sel, off_y, off_pl, off_mv, off_sws;
   // refinement (A0 == nullptr: none)
   const double* A0;
   const double* B;
@@ -868,7 +861,7 @@ struct PlanProblem {
 enum OpKind { OP_SRRQR = 0, OP_GEPP, OP_MOVES, OP_L21, OP_U12, OP_SCHUR };
 struct PlanOp {
   OpKind kind;
-  size_t off;          // byte offset of the work list in plan memory
+  size_t off;          // byte offset of the work list in the workspace
   int count;
   int bw;
   int64_t max_a, max_b;
@@ -876,8 +869,30 @@ struct PlanOp {
   int srrqr_index;     // OP_SRRQR: index into srrqr_args
 };
 
-struct BatchPlan {
+constexpr int kForks = 4;
+
+struct ForkPool {
+  int dev = -1;
+  hipStream_t s[kForks] = {};
+};
+ForkPool g_forks;
+
+hipError_t fork_streams(hipStream_t** out) {
   int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (g_forks.dev != dev) {
+    for (auto& f : g_forks.s) {
+      e = hipStreamCreateWithFlags(&f, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    g_forks.dev = dev;
+  }
+  *out = g_forks.s;
+  return hipSuccess;
+}
+
+struct BatchPlan {
   double tau = 2.0;
   int schur = 0;
   int rpw_target = 64;
@@ -885,35 +900,231 @@ struct BatchPlan {
   int max_iter = 0;
   bool refine = false;
   std::vector<PlanProblem> p;
-  char* dmem = nullptr;
-  size_t dbytes = 0;
-  uint64_t* slots_all = nullptr;
-  size_t slots_words = 0;
-  uint32_t* abort = nullptr;
-  int32_t* iters = nullptr;     // [count] refinement iterations
-  double* rels = nullptr;       // [count] last correction ratio
+  char* base = nullptr;             // workspace
+  size_t need = 0;
+  size_t lists_at = 0;
+  size_t slots_begin = 0, slots_end = 0;
+  size_t off_abort = 0, off_iters = 0, off_rels = 0;
+  std::vector<char> host;           // work lists (host image, uploaded at creation)
   std::vector<PlanOp> ops;
   std::vector<SrrqrArgs> srrqr_args;
+  std::vector<size_t> srrqr_list_off;
   int nforks = 0;
-  hipStream_t forks[4] = {};
+  hipStream_t* forks = nullptr;
   hipEvent_t ev_fork = nullptr;
-  hipEvent_t ev_join[4] = {};
-  hipStream_t cap = nullptr;     // private stream the graph is captured on
+  hipEvent_t ev_join[kForks] = {};
+  hipStream_t cap = nullptr;        // private stream the graph is captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
+// Lays out the workspace and builds every step's work lists (offsets stand in
+// for device pointers until relocate(); no offset is 0, which means "none").
+void plan_build(BatchPlan& P) {
+  const int cap = std::min(256, device_cus());
+  const int64_t count = (int64_t)P.p.size();
+  size_t off = 256;
+  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes, 256); return o; };
+  P.slots_begin = off;
+  for (auto& q : P.p) {
+    q.Gmax = groups_for_rows(q.n, cap, 64);
+    q.set_words = (size_t)q.Gmax * kRoundsMax * kPostW;
+    q.off_slots = take(2 * q.set_words * 8);
+  }
+  P.slots_end = off;
+  for (auto& q : P.p) {
+    q.off_rounds = take(2 * 4);
+    q.off_sel = take(kMaxB * 4);
+    q.off_y = take((size_t)q.n * q.b * 8);
+    q.off_pl = take((size_t)q.b * q.b * 8);
+    q.off_mv = take((4 * kMaxB + 4) * 4);
+    q.off_sws = 0;
+    if (P.refine) {
+      prrp_solve_workspace_size(q.n, q.nrhs, &q.sws_bytes);
+      q.off_sws = take(q.sws_bytes);
+    }
+  }
+  P.off_abort = take(256);
+  P.off_iters = take((size_t)count * 4);
+  P.off_rels = take((size_t)count * 8);
+  P.lists_at = align_up(off, 256);
+
+  std::vector<char>& host = P.host;
+  host.clear();
+  auto put = [&](const void* src, size_t bytes) {
+    const size_t o = align_up(host.size(), 256);
+    host.resize(o + bytes);
+    std::memcpy(host.data() + o, src, bytes);
+    return o;
+  };
+  auto W = [](size_t o) { return reinterpret_cast<char*>(o); };   // offset as pointer
+  std::vector<int> prevG(count, 0), prevBw(count, 0);
+  int64_t steps = 0;
+  for (auto& q : P.p) steps = std::max<int64_t>(steps, (q.n + q.b - 1) / q.b);
+  for (int64_t s = 0; s < steps; ++s) {
+    const int par = (int)(s & 1);
+    std::vector<std::pair<std::pair<int, int>, int>> cls;   // ((bw, G), problem)
+    for (int64_t i = 0; i < count; ++i) {
+      const PlanProblem& q = P.p[i];
+      const int64_t k0 = s * q.b;
+      if (k0 >= q.n) continue;
+      const int64_t m = q.n - k0;
+      const int bw = (int)std::min<int64_t>(q.b, m);
+      cls.push_back({{bw, groups_for_rows(m, cap, P.rpw_target)}, (int)i});
+    }
+    std::stable_sort(cls.begin(), cls.end(),
+                     [](const auto& x, const auto& y) { return x.first < y.first; });
+    for (size_t c0 = 0; c0 < cls.size();) {
+      size_t c1 = c0;
+      while (c1 < cls.size() && cls[c1].first == cls[c0].first) ++c1;
+      const int bw = cls[c0].first.first, G = cls[c0].first.second;
+      std::vector<SrrqrProblem> list;
+      int64_t maxm = 0;
+      for (size_t c = c0; c < c1; ++c) {
+        const int i = cls[c].second;
+        const PlanProblem& q = P.p[i];
+        const int64_t k0 = s * q.b, m = q.n - k0;
+        maxm = std::max(maxm, m);
+        SrrqrProblem sp;
+        std::memset(&sp, 0, sizeof sp);
+        sp.A = q.A; sp.lda = q.lda; sp.k0 = k0; sp.m = (int)m;
+        sp.Y = (m > bw) ? reinterpret_cast<double*>(W(q.off_y)) : nullptr;
+        sp.ldy = q.b;
+        sp.sel_out = reinterpret_cast<int32_t*>(W(q.off_sel));
+        sp.slots = reinterpret_cast<uint64_t*>(W(q.off_slots + (size_t)par * q.set_words * 8));
+        sp.rounds_out = reinterpret_cast<int32_t*>(W(q.off_rounds + (size_t)par * 4));
+        if (s > 0) {
+          sp.clear_base = reinterpret_cast<uint64_t*>(W(q.off_slots + (size_t)(1 - par) * q.set_words * 8));
+          sp.clear_G = prevG[i];
+          sp.clear_bw = prevBw[i];
+          sp.clear_rounds = reinterpret_cast<int32_t*>(W(q.off_rounds + (size_t)(1 - par) * 4));
+        }
+        sp.stats = q.stats;
+        list.push_back(sp);
+        prevG[i] = G;
+        prevBw[i] = bw;
+      }
+      SrrqrArgs a;
+      std::memset(&a, 0, sizeof a);
+      a.bw = bw;
+      a.ngroups = (int)list.size();
+      a.G = G;
+      a.rpw = (int)((maxm + G - 1) / G);
+      a.mode = 0;
+      a.tau_bits = tau_bits(P.tau);
+      a.report_rank = 1;
+      a.record_block_L = 1;
+      const size_t lo = put(list.data(), list.size() * sizeof(SrrqrProblem));
+      P.ops.push_back(PlanOp{OP_SRRQR, lo, (int)list.size(), bw, 0, 0, 0, (int)P.srrqr_args.size()});
+      P.srrqr_args.push_back(a);
+      P.srrqr_list_off.push_back(lo);
+      c0 = c1;
+    }
+    std::vector<GeppArgs> gl;
+    std::vector<MoveArgs> ml;
+    std::vector<GemmArgs> l21, sch;
+    std::vector<TrsmArgs> tl;
+    int maxbw = 0;
+    int64_t maxout = 0, maxm2 = 0, maxnr = 0;
+    for (int64_t i = 0; i < count; ++i) {
+      const PlanProblem& q = P.p[i];
+      const int64_t k0 = s * q.b;
+      if (k0 >= q.n) continue;
+      const int64_t m = q.n - k0;
+      const int bw = (int)std::min<int64_t>(q.b, m);
+      maxbw = std::max(maxbw, bw);
+      int32_t* mv_dst = reinterpret_cast<int32_t*>(W(q.off_mv));
+      int32_t* mv_src = reinterpret_cast<int32_t*>(W(q.off_mv + 2 * kMaxB * 4));
+      int32_t* n_moves = reinterpret_cast<int32_t*>(W(q.off_mv + 4 * kMaxB * 4));
+      double* Yp = reinterpret_cast<double*>(W(q.off_y));
+      double* PLp = reinterpret_cast<double*>(W(q.off_pl));
+      gl.push_back(GeppArgs{q.A, q.lda, k0, bw, (int)m, reinterpret_cast<int32_t*>(W(q.off_sel)),
+                            PLp, mv_dst, mv_src, n_moves, q.stats});
+      ml.push_back(MoveArgs{q.A, q.lda, q.n, k0, bw, mv_dst, mv_src, n_moves, q.perm,
+                            (m > bw) ? Yp : nullptr, q.b});
+      maxout = std::max<int64_t>(maxout, q.n - bw);
+      if (m > bw) {
+        const int64_t nr = q.n - k0 - bw;
+        // Y rows from bw on: offset of Y plus bw rows of ld b
+        double* Yrows = reinterpret_cast<double*>(W(q.off_y + (size_t)bw * q.b * 8));
+        l21.push_back(GemmArgs{(int)(m - bw), bw, bw, Yrows, q.b, PLp, bw,
+                               q.A + (k0 + bw) * q.lda + k0, q.lda, 1.0, 0.0, nullptr, nullptr,
+                               PRRP_FP64});
+        tl.push_back(TrsmArgs{q.A, q.lda, k0, bw, nr, &q.stats->max_abs_U, &q.stats->max_abs_W});
+        sch.push_back(GemmArgs{(int)(m - bw), (int)nr, bw, q.A + (k0 + bw) * q.lda + k0, q.lda,
+                               q.A + k0 * q.lda + k0 + bw, q.lda, q.A + (k0 + bw) * q.lda + k0 + bw,
+                               q.lda, -1.0, 1.0, &q.stats->max_abs_W, nullptr, P.schur});
+        maxm2 = std::max<int64_t>(maxm2, m - bw);
+        maxnr = std::max<int64_t>(maxnr, nr);
+      }
+    }
+    P.ops.push_back(PlanOp{OP_GEPP, put(gl.data(), gl.size() * sizeof(GeppArgs)), (int)gl.size(),
+                           maxbw, 0, 0, 0, -1});
+    P.ops.push_back(PlanOp{OP_MOVES, put(ml.data(), ml.size() * sizeof(MoveArgs)), (int)ml.size(),
+                           maxbw, maxout, 0, 0, -1});
+    if (!l21.empty()) {
+      P.ops.push_back(PlanOp{OP_L21, put(l21.data(), l21.size() * sizeof(GemmArgs)),
+                             (int)l21.size(), maxbw, maxm2, maxbw, PRRP_FP64, -1});
+      P.ops.push_back(PlanOp{OP_U12, put(tl.data(), tl.size() * sizeof(TrsmArgs)), (int)tl.size(),
+                             maxbw, maxnr, 0, 0, -1});
+      P.ops.push_back(PlanOp{OP_SCHUR, put(sch.data(), sch.size() * sizeof(GemmArgs)),
+                             (int)sch.size(), maxbw, maxm2, maxnr, P.schur, -1});
+    }
+  }
+  P.need = P.lists_at + host.size();
+}
+
+// Turns the offsets in the work lists into addresses in the workspace.
+void plan_relocate(BatchPlan& P) {
+  char* base = P.base;
+  auto R = [&](auto*& ptr) {
+    if (ptr != nullptr)
+      ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(
+          base + reinterpret_cast<size_t>(ptr));
+  };
+  for (size_t k = 0; k < P.srrqr_args.size(); ++k) {
+    SrrqrProblem* lst = reinterpret_cast<SrrqrProblem*>(P.host.data() + P.srrqr_list_off[k]);
+    for (int g = 0; g < P.srrqr_args[k].ngroups; ++g) {
+      SrrqrProblem& sp = lst[g];
+      R(sp.Y); R(sp.sel_out); R(sp.slots); R(sp.rounds_out); R(sp.clear_base); R(sp.clear_rounds);
+    }
+    P.srrqr_args[k].probs =
+        reinterpret_cast<const SrrqrProblem*>(base + P.lists_at + P.srrqr_list_off[k]);
+    P.srrqr_args[k].abort_flag = reinterpret_cast<uint32_t*>(base + P.off_abort);
+  }
+  for (PlanOp& o : P.ops) {
+    char* h = P.host.data() + o.off;
+    if (o.kind == OP_GEPP) {
+      GeppArgs* g = reinterpret_cast<GeppArgs*>(h);
+      for (int k = 0; k < o.count; ++k) {
+        R(g[k].sel); R(g[k].PL); R(g[k].mv_dst); R(g[k].mv_src); R(g[k].n_moves);
+      }
+    } else if (o.kind == OP_MOVES) {
+      MoveArgs* m = reinterpret_cast<MoveArgs*>(h);
+      for (int k = 0; k < o.count; ++k) { R(m[k].mv_dst); R(m[k].mv_src); R(m[k].n_moves); R(m[k].Y); }
+    } else if (o.kind == OP_L21) {
+      GemmArgs* g = reinterpret_cast<GemmArgs*>(h);
+      for (int k = 0; k < o.count; ++k) { R(g[k].A); R(g[k].B); }
+    }
+    o.off += P.lists_at;
+  }
+  for (auto& q : P.p)
+    if (P.refine) q.sws = base + q.off_sws;
+}
+
 hipError_t plan_enqueue(BatchPlan& P, hipStream_t st) {
   hipError_t e;
+  uint32_t* abort_flag = reinterpret_cast<uint32_t*>(P.base + P.off_abort);
   for (auto& q : P.p) {
-    e = launch_init_factor(q.A, q.n, q.lda, q.perm, q.stats, P.abort, 0,
+    e = launch_init_factor(q.A, q.n, q.lda, q.perm, q.stats, abort_flag, 0,
                            (int)((q.n + q.b - 1) / q.b), st);
     if (e != hipSuccess) return e;
   }
-  e = launch_fill_u64(P.slots_all, P.slots_words, kKeySent, st);
+  e = launch_fill_u64(reinterpret_cast<uint64_t*>(P.base + P.slots_begin),
+                      (P.slots_end - P.slots_begin) / 8, kKeySent, st);
   if (e != hipSuccess) return e;
   for (const PlanOp& o : P.ops) {
-    char* list = P.dmem + o.off;
+    char* list = P.base + o.off;
     switch (o.kind) {
       case OP_SRRQR: e = launch_srrqr(P.srrqr_args[o.srrqr_index], st); break;
       case OP_GEPP: e = launch_gepp_batched(reinterpret_cast<GeppArgs*>(list), o.count, o.bw, st); break;
@@ -932,6 +1143,8 @@ hipError_t plan_enqueue(BatchPlan& P, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   if (P.refine) {
+    int32_t* iters = reinterpret_cast<int32_t*>(P.base + P.off_iters);
+    double* rels = reinterpret_cast<double*>(P.base + P.off_rels);
     e = hipEventRecord(P.ev_fork, st);
     if (e != hipSuccess) return e;
     for (int f = 0; f < P.nforks; ++f) {
@@ -940,11 +1153,10 @@ hipError_t plan_enqueue(BatchPlan& P, hipStream_t st) {
     }
     for (size_t i = 0; i < P.p.size(); ++i) {
       const PlanProblem& q = P.p[i];
-      if (!q.A0) continue;
       hipStream_t fs = P.forks[i % P.nforks];
       const int rc = prrp_refine_async(q.A0, q.A, q.n, q.lda, q.perm, q.B, q.X, q.nrhs, q.nrhs,
-                                       P.tol, P.max_iter, P.iters + i, P.rels + i, q.sws,
-                                       q.sws_bytes, fs);
+                                       P.tol, P.max_iter, iters + i, rels + i, q.sws, q.sws_bytes,
+                                       fs);
       if (rc != 0) return hipErrorInvalidValue;
     }
     for (int f = 0; f < P.nforks; ++f) {
@@ -961,25 +1173,18 @@ void plan_free(BatchPlan* P) {
   if (!P) return;
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   if (P->graph) (void)hipGraphDestroy(P->graph);
-  for (int f = 0; f < P->nforks; ++f) {
-    if (P->forks[f]) (void)hipStreamDestroy(P->forks[f]);
+  for (int f = 0; f < kForks; ++f)
     if (P->ev_join[f]) (void)hipEventDestroy(P->ev_join[f]);
-  }
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->cap) (void)hipStreamDestroy(P->cap);
-  if (P->dmem) (void)hipFree(P->dmem);
   delete P;
 }
 
-}  // namespace
-
-extern "C" {
-
-int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
-                           const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
-                           int schur, int rows_per_wg, const double* const* A0,
-                           const double* const* B, double* const* X, const int64_t* nrhs,
-                           double tol, int max_iter, void** plan_out) {
+int plan_setup(BatchPlan& P, int64_t count, double* const* A, const int64_t* n,
+               const int64_t* lda, const int* b, int64_t* const* perm, prrp_stats* stats,
+               double tau, int schur, int rows_per_wg, const double* const* A0,
+               const double* const* B, double* const* X, const int64_t* nrhs, double tol,
+               int max_iter) {
   if (count < 1 || count > 4096) return -1;
   if (!A) return -2;
   if (!n) return -3;
@@ -993,7 +1198,6 @@ int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, co
   const bool refine = A0 != nullptr;
   if (refine && (!B || !X || !nrhs)) return -11;
   if (refine && (!(tol >= 0.0) || max_iter < 0 || max_iter > 1000)) return -15;
-  if (!plan_out) return -17;
   for (int64_t i = 0; i < count; ++i) {
     if (!A[i] || !perm[i]) return -2;
     if (n[i] < 1 || n[i] > kMaxN) return -3;
@@ -1001,252 +1205,82 @@ int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, co
     if (b[i] < 1 || b[i] > kMaxB || b[i] > n[i]) return -5;
     if (refine && (!A0[i] || !B[i] || !X[i] || nrhs[i] < 1)) return -11;
   }
-  PRRP_TRY(srrqr_prepare());
-  BatchPlan* P = new BatchPlan();
-  P->tau = tau;
-  P->schur = schur;
-  P->rpw_target = rows_per_wg;
-  P->refine = refine;
-  P->tol = tol;
-  P->max_iter = max_iter;
-  if (hipGetDevice(&P->dev) != hipSuccess) { delete P; return -1000; }
-  const int cap = std::min(256, device_cus());
-
-  // ---- per-problem workspaces.  Work lists below hold plan offsets in place
-  // of device pointers until relocation, with 0 meaning "none", so no real
-  // offset may be 0.
-  size_t off = 256;
-  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes, 256); return o; };
-  struct Offs { size_t slots, rounds, sel, y, pl, mv, sws; };
-  std::vector<Offs> po(count);
-  P->p.resize(count);
-  size_t slots_begin = 0, slots_end = 0;
+  P.tau = tau;
+  P.schur = schur;
+  P.rpw_target = rows_per_wg;
+  P.refine = refine;
+  P.tol = tol;
+  P.max_iter = max_iter;
+  P.p.resize(count);
   for (int64_t i = 0; i < count; ++i) {
-    PlanProblem& q = P->p[i];
+    PlanProblem& q = P.p[i];
+    std::memset(&q, 0, sizeof q);
     q.A = A[i]; q.n = n[i]; q.lda = lda[i]; q.b = b[i]; q.perm = perm[i]; q.stats = stats + i;
-    q.Gmax = groups_for_rows(q.n, cap, 64);
-    q.set_words = (size_t)q.Gmax * kRoundsMax * kPostW;
-    po[i].slots = take(2 * q.set_words * 8);
-    if (i == 0) slots_begin = po[i].slots;
-    slots_end = off;
+    if (refine) { q.A0 = A0[i]; q.B = B[i]; q.X = X[i]; q.nrhs = nrhs[i]; }
   }
-  for (int64_t i = 0; i < count; ++i) {
-    PlanProblem& q = P->p[i];
-    po[i].rounds = take(2 * 4);
-    po[i].sel = take(kMaxB * 4);
-    po[i].y = take((size_t)q.n * q.b * 8);
-    po[i].pl = take((size_t)q.b * q.b * 8);
-    po[i].mv = take((4 * kMaxB + 4) * 4);
-    q.A0 = nullptr;
-    if (refine) {
-      q.A0 = A0[i]; q.B = B[i]; q.X = X[i]; q.nrhs = nrhs[i];
-      prrp_solve_workspace_size(q.n, q.nrhs, &q.sws_bytes);
-      po[i].sws = take(q.sws_bytes);
-    }
-  }
-  const size_t off_abort = take(256);
-  const size_t off_iters = take((size_t)count * 4);
-  const size_t off_rels = take((size_t)count * 8);
+  plan_build(P);
+  return 0;
+}
 
-  // ---- work lists, step by step (host image, device offsets)
-  std::vector<char> host;
-  auto put = [&](const void* src, size_t bytes) {
-    const size_t o = align_up(host.size(), 256);
-    host.resize(o + bytes);
-    std::memcpy(host.data() + o, src, bytes);
-    return o;
-  };
-  std::vector<int> prevG(count, 0), prevBw(count, 0);
-  int64_t steps = 0;
-  for (int64_t i = 0; i < count; ++i) steps = std::max<int64_t>(steps, (n[i] + b[i] - 1) / b[i]);
-  struct SrrqrOpHost { SrrqrArgs a; size_t list_off; };
-  std::vector<SrrqrOpHost> sops;
-  for (int64_t s = 0; s < steps; ++s) {
-    const int par = (int)(s & 1);
-    // strong RRQR: classes of equal (bw, G)
-    std::vector<std::pair<std::pair<int, int>, int>> cls;   // ((bw, G), problem)
-    for (int64_t i = 0; i < count; ++i) {
-      const PlanProblem& q = P->p[i];
-      const int64_t k0 = s * q.b;
-      if (k0 >= q.n) continue;
-      const int64_t m = q.n - k0;
-      const int bw = (int)std::min<int64_t>(q.b, m);
-      cls.push_back({{bw, groups_for_rows(m, cap, rows_per_wg)}, (int)i});
-    }
-    std::stable_sort(cls.begin(), cls.end(),
-                     [](const auto& x, const auto& y) { return x.first < y.first; });
-    for (size_t c0 = 0; c0 < cls.size();) {
-      size_t c1 = c0;
-      while (c1 < cls.size() && cls[c1].first == cls[c0].first) ++c1;
-      const int bw = cls[c0].first.first, G = cls[c0].first.second;
-      std::vector<SrrqrProblem> list;
-      int64_t maxm = 0;
-      for (size_t c = c0; c < c1; ++c) {
-        const int i = cls[c].second;
-        PlanProblem& q = P->p[i];
-        const int64_t k0 = s * q.b, m = q.n - k0;
-        maxm = std::max(maxm, m);
-        SrrqrProblem sp;
-        std::memset(&sp, 0, sizeof sp);
-        sp.A = q.A; sp.lda = q.lda; sp.k0 = k0; sp.m = (int)m;
-        sp.Y = (m > bw) ? reinterpret_cast<double*>(po[i].y) : nullptr;   // offsets, fixed below
-        sp.ldy = q.b;
-        sp.sel_out = reinterpret_cast<int32_t*>(po[i].sel);
-        sp.slots = reinterpret_cast<uint64_t*>(po[i].slots + (size_t)par * q.set_words * 8);
-        sp.rounds_out = reinterpret_cast<int32_t*>(po[i].rounds + (size_t)par * 4);
-        if (s > 0) {
-          sp.clear_base = reinterpret_cast<uint64_t*>(po[i].slots + (size_t)(1 - par) * q.set_words * 8);
-          sp.clear_G = prevG[i];
-          sp.clear_bw = prevBw[i];
-          sp.clear_rounds = reinterpret_cast<int32_t*>(po[i].rounds + (size_t)(1 - par) * 4);
-        }
-        sp.stats = q.stats;
-        list.push_back(sp);
-        prevG[i] = G;
-        prevBw[i] = bw;
-      }
-      SrrqrOpHost so;
-      std::memset(&so.a, 0, sizeof so.a);
-      so.a.bw = bw;
-      so.a.ngroups = (int)list.size();
-      so.a.G = G;
-      so.a.rpw = (int)((maxm + G - 1) / G);
-      so.a.mode = 0;
-      so.a.tau_bits = tau_bits(tau);
-      so.a.report_rank = 1;
-      so.a.record_block_L = 1;
-      so.list_off = put(list.data(), list.size() * sizeof(SrrqrProblem));
-      PlanOp op{OP_SRRQR, so.list_off, (int)list.size(), bw, 0, 0, 0, (int)sops.size()};
-      sops.push_back(so);
-      P->ops.push_back(op);
-      c0 = c1;
-    }
-    // diagonal GEPP, moves, L21, U12, Schur: one launch each
-    std::vector<GeppArgs> gl;
-    std::vector<MoveArgs> ml;
-    std::vector<GemmArgs> l21, sch;
-    std::vector<TrsmArgs> tl;
-    int maxbw = 0;
-    int64_t maxout = 0, maxl21m = 0, maxnr = 0, maxschm = 0;
-    for (int64_t i = 0; i < count; ++i) {
-      PlanProblem& q = P->p[i];
-      const int64_t k0 = s * q.b;
-      if (k0 >= q.n) continue;
-      const int64_t m = q.n - k0;
-      const int bw = (int)std::min<int64_t>(q.b, m);
-      maxbw = std::max(maxbw, bw);
-      int32_t* mvp = reinterpret_cast<int32_t*>(po[i].mv);
-      int32_t* mv_dst = mvp;
-      int32_t* mv_src = mvp + 2 * kMaxB;
-      int32_t* n_moves = mvp + 4 * kMaxB;
-      double* Yp = reinterpret_cast<double*>(po[i].y);
-      double* PLp = reinterpret_cast<double*>(po[i].pl);
-      gl.push_back(GeppArgs{q.A, q.lda, k0, bw, (int)m, reinterpret_cast<int32_t*>(po[i].sel), PLp,
-                            mv_dst, mv_src, n_moves, q.stats});
-      ml.push_back(MoveArgs{q.A, q.lda, q.n, k0, bw, mv_dst, mv_src, n_moves, q.perm,
-                            (m > bw) ? Yp : nullptr, q.b});
-      maxout = std::max<int64_t>(maxout, q.n - bw);
-      if (m > bw) {
-        const int64_t nr = q.n - k0 - bw;
-        l21.push_back(GemmArgs{(int)(m - bw), bw, bw, Yp + (size_t)bw * q.b, q.b, PLp, bw,
-                               q.A + (k0 + bw) * q.lda + k0, q.lda, 1.0, 0.0, nullptr, nullptr,
-                               PRRP_FP64});
-        tl.push_back(TrsmArgs{q.A, q.lda, k0, bw, nr, &q.stats->max_abs_U, &q.stats->max_abs_W});
-        sch.push_back(GemmArgs{(int)(m - bw), (int)nr, bw, q.A + (k0 + bw) * q.lda + k0, q.lda,
-                               q.A + k0 * q.lda + k0 + bw, q.lda, q.A + (k0 + bw) * q.lda + k0 + bw,
-                               q.lda, -1.0, 1.0, &q.stats->max_abs_W, nullptr, schur});
-        maxl21m = std::max<int64_t>(maxl21m, m - bw);
-        maxnr = std::max<int64_t>(maxnr, nr);
-        maxschm = std::max<int64_t>(maxschm, m - bw);
-      }
-    }
-    P->ops.push_back(PlanOp{OP_GEPP, put(gl.data(), gl.size() * sizeof(GeppArgs)), (int)gl.size(),
-                            maxbw, 0, 0, 0, -1});
-    P->ops.push_back(PlanOp{OP_MOVES, put(ml.data(), ml.size() * sizeof(MoveArgs)), (int)ml.size(),
-                            maxbw, maxout, 0, 0, -1});
-    if (!l21.empty()) {
-      P->ops.push_back(PlanOp{OP_L21, put(l21.data(), l21.size() * sizeof(GemmArgs)),
-                              (int)l21.size(), maxbw, maxl21m, maxbw, PRRP_FP64, -1});
-      P->ops.push_back(PlanOp{OP_U12, put(tl.data(), tl.size() * sizeof(TrsmArgs)), (int)tl.size(),
-                              maxbw, maxnr, 0, 0, -1});
-      P->ops.push_back(PlanOp{OP_SCHUR, put(sch.data(), sch.size() * sizeof(GemmArgs)),
-                              (int)sch.size(), maxbw, maxschm, maxnr, schur, -1});
-    }
-  }
+}  // namespace
 
-  // ---- device memory: workspaces, then the work lists
-  const size_t lists_at = align_up(off, 256);
-  P->dbytes = lists_at + host.size();
-  if (hipMalloc(&P->dmem, P->dbytes) != hipSuccess) { plan_free(P); return -1002; }
-  char* base = P->dmem;
-  auto dptr = [&](size_t o) { return base + o; };
-  // relocate workspace offsets stored as pointers into device addresses
-  for (auto& so : sops) {
-    SrrqrProblem* lst = reinterpret_cast<SrrqrProblem*>(host.data() + so.list_off);
-    for (int g = 0; g < so.a.ngroups; ++g) {
-      SrrqrProblem& sp = lst[g];
-      if (sp.Y) sp.Y = reinterpret_cast<double*>(dptr(reinterpret_cast<size_t>(sp.Y)));
-      sp.sel_out = reinterpret_cast<int32_t*>(dptr(reinterpret_cast<size_t>(sp.sel_out)));
-      sp.slots = reinterpret_cast<uint64_t*>(dptr(reinterpret_cast<size_t>(sp.slots)));
-      sp.rounds_out = reinterpret_cast<int32_t*>(dptr(reinterpret_cast<size_t>(sp.rounds_out)));
-      if (sp.clear_base) {
-        sp.clear_base = reinterpret_cast<uint64_t*>(dptr(reinterpret_cast<size_t>(sp.clear_base)));
-        sp.clear_rounds = reinterpret_cast<const int32_t*>(
-            dptr(reinterpret_cast<size_t>(sp.clear_rounds)));
-      }
-    }
-    so.a.probs = reinterpret_cast<const SrrqrProblem*>(base + lists_at + so.list_off);
-    so.a.abort_flag = reinterpret_cast<uint32_t*>(base + off_abort);
-    P->srrqr_args.push_back(so.a);
+extern "C" {
+
+int prrp_batch_plan_workspace_size(int64_t count, const int64_t* n, const int* b,
+                                   const int64_t* nrhs, int rows_per_wg, size_t* bytes) {
+  if (count < 1 || count > 4096) return -1;
+  if (!n) return -2;
+  if (!b) return -3;
+  if (rows_per_wg != 64 && rows_per_wg != 128) return -5;
+  if (!bytes) return -6;
+  std::vector<double*> fakeA(count, reinterpret_cast<double*>(8));
+  std::vector<int64_t*> fakeP(count, reinterpret_cast<int64_t*>(8));
+  std::vector<const double*> fakeA0(count, reinterpret_cast<const double*>(8));
+  std::vector<double*> fakeX(count, reinterpret_cast<double*>(8));
+  std::vector<int64_t> lda(n, n + count);
+  BatchPlan P;
+  const int rc = plan_setup(P, count, fakeA.data(), n, lda.data(), b, fakeP.data(),
+                            reinterpret_cast<prrp_stats*>(8), 2.0, 0, rows_per_wg,
+                            nrhs ? fakeA0.data() : nullptr, nrhs ? fakeA0.data() : nullptr,
+                            nrhs ? fakeX.data() : nullptr, nrhs, 0.0, 1);
+  if (rc == -3 || rc == -4) return -2;
+  if (rc == -5) return -3;
+  if (rc == -11) return -4;
+  if (rc) return rc;
+  *bytes = P.need;
+  return 0;
+}
+
+int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
+                           const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
+                           int schur, int rows_per_wg, const double* const* A0,
+                           const double* const* B, double* const* X, const int64_t* nrhs,
+                           double tol, int max_iter, void* workspace, size_t ws_bytes,
+                           void* stream, void** plan_out) {
+  if (!plan_out) return -20;
+  BatchPlan* P = new BatchPlan();
+  int rc = plan_setup(*P, count, A, n, lda, b, perm, stats, tau, schur, rows_per_wg, A0, B, X,
+                      nrhs, tol, max_iter);
+  if (rc) { plan_free(P); return rc; }
+  if (!workspace) { plan_free(P); return -17; }
+  if (ws_bytes < P->need) { plan_free(P); return -18; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = srrqr_prepare();
+  if (e == hipSuccess) e = prepare_batched_kernels();
+  if (e == hipSuccess && P->refine) {
+    e = fork_streams(&P->forks);
+    P->nforks = (int)std::min<int64_t>(kForks, count);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
+    for (int f = 0; f < P->nforks && e == hipSuccess; ++f)
+      e = hipEventCreateWithFlags(&P->ev_join[f], hipEventDisableTiming);
   }
-  for (PlanOp& o : P->ops) {
-    const size_t lo = o.off;
-    char* h = host.data() + lo;
-    auto fixp = [&](auto*& ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(
-                                      dptr(reinterpret_cast<size_t>(ptr))); };
-    if (o.kind == OP_GEPP) {
-      GeppArgs* g = reinterpret_cast<GeppArgs*>(h);
-      for (int k = 0; k < o.count; ++k) {
-        fixp(g[k].sel); fixp(g[k].PL); fixp(g[k].mv_dst); fixp(g[k].mv_src); fixp(g[k].n_moves);
-      }
-    } else if (o.kind == OP_MOVES) {
-      MoveArgs* m = reinterpret_cast<MoveArgs*>(h);
-      for (int k = 0; k < o.count; ++k) {
-        fixp(m[k].mv_dst); fixp(m[k].mv_src); fixp(m[k].n_moves);
-        if (m[k].Y) fixp(m[k].Y);
-      }
-    } else if (o.kind == OP_L21) {
-      GemmArgs* g = reinterpret_cast<GemmArgs*>(h);
-      for (int k = 0; k < o.count; ++k) { fixp(g[k].A); fixp(g[k].B); }
-    }
-    o.off = lists_at + lo;
-  }
-  P->slots_all = reinterpret_cast<uint64_t*>(base + slots_begin);
-  P->slots_words = (slots_end - slots_begin) / 8;
-  P->abort = reinterpret_cast<uint32_t*>(base + off_abort);
-  P->iters = reinterpret_cast<int32_t*>(base + off_iters);
-  P->rels = reinterpret_cast<double*>(base + off_rels);
-  if (refine) {
-    for (int64_t i = 0; i < count; ++i) P->p[i].sws = base + po[i].sws;
-  }
-  if (hipMemcpy(base + lists_at, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    plan_free(P);
-    return -1003;
-  }
-  if (refine) {
-    P->nforks = (int)std::min<int64_t>(4, count);
-    if (hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess) {
-      plan_free(P);
-      return -1004;
-    }
-    for (int f = 0; f < P->nforks; ++f) {
-      if (hipStreamCreateWithFlags(&P->forks[f], hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&P->ev_join[f], hipEventDisableTiming) != hipSuccess) {
-        plan_free(P);
-        return -1004;
-      }
-    }
-  }
+  if (e != hipSuccess) { plan_free(P); return herr(e); }
+  P->base = static_cast<char*>(workspace);
+  plan_relocate(*P);
+  // the host image stays alive in the plan until destruction
+  e = hipMemcpyAsync(P->base + P->lists_at, P->host.data(), P->host.size(),
+                     hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) { plan_free(P); return herr(e); }
   *plan_out = P;
   return 0;
 }
@@ -1272,12 +1306,14 @@ int prrp_batch_plan_run(void* plan, void* stream, int use_graph) {
   return herr(hipGraphLaunch(P.exec, st));
 }
 
-int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels) {
+int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels, void* stream) {
   if (!plan) return -1;
   BatchPlan& P = *static_cast<BatchPlan*>(plan);
+  hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t c = P.p.size();
-  if (iters) PRRP_TRY(hipMemcpy(iters, P.iters, c * 4, hipMemcpyDeviceToHost));
-  if (rels) PRRP_TRY(hipMemcpy(rels, P.rels, c * 8, hipMemcpyDeviceToHost));
+  if (iters) PRRP_TRY(hipMemcpyAsync(iters, P.base + P.off_iters, c * 4, hipMemcpyDeviceToHost, st));
+  if (rels) PRRP_TRY(hipMemcpyAsync(rels, P.base + P.off_rels, c * 8, hipMemcpyDeviceToHost, st));
+  PRRP_TRY(hipStreamSynchronize(st));
   return 0;
 }
 
@@ -1289,13 +1325,18 @@ int prrp_batch_plan_destroy(void* plan) {
 int prrp_factor_batched(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
                         const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
                         int schur, void* stream) {
-  void* plan = nullptr;
-  int rc = prrp_batch_plan_create(count, A, n, lda, b, perm, stats, tau, schur, 64, nullptr,
-                                  nullptr, nullptr, nullptr, 0.0, 0, &plan);
+  size_t need = 0;
+  int rc = prrp_batch_plan_workspace_size(count, n, b, nullptr, 64, &need);
   if (rc) return rc;
-  rc = prrp_batch_plan_run(plan, stream, 0);
+  void* ws = nullptr;
+  if (hipMalloc(&ws, need) != hipSuccess) return -1002;
+  void* plan = nullptr;
+  rc = prrp_batch_plan_create(count, A, n, lda, b, perm, stats, tau, schur, 64, nullptr, nullptr,
+                              nullptr, nullptr, 0.0, 0, ws, need, stream, &plan);
+  if (rc == 0) rc = prrp_batch_plan_run(plan, stream, 0);
   const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
-  prrp_batch_plan_destroy(plan);
+  if (plan) prrp_batch_plan_destroy(plan);
+  (void)hipFree(ws);
   if (rc) return rc;
   return herr(e);
 }

@@ -519,6 +519,16 @@ hipError_t launch_trsm_u12(double* A, int64_t lda, int64_t k0, int bw, int64_t n
   return hipGetLastError();
 }
 
+hipError_t prepare_batched_kernels() {
+  hipError_t e = hipFuncSetAttribute((const void*)gepp_batched_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)gepp_smem_bytes(kMaxB));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)trsm_u12_batched_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(double) * (size_t)(kMaxB * (kMaxB - 1) / 2 + 1)));
+}
+
 hipError_t launch_trsm_u12_batched(const TrsmArgs* list, int count, int bw, int64_t max_nr,
                                    hipStream_t stream) {
   if (count <= 0 || max_nr <= 0) return hipSuccess;

@@ -117,6 +117,8 @@ hipError_t launch_moves_batched(const MoveArgs* list, int count, int64_t max_out
                                 hipStream_t stream);
 hipError_t launch_trsm_u12_batched(const TrsmArgs* list, int count, int bw, int64_t max_nr,
                                    hipStream_t stream);
+// Raises the dynamic LDS limit of the batched kernels (before graph capture).
+hipError_t prepare_batched_kernels();
 
 // -------------------------------------------------------------- GEMMs
 // C = alpha * A * B + beta * C, row-major, FP64 operands; the Schur variants

@@ -117,12 +117,23 @@ def test_batch_plan_argument_errors(L):
         a = args(**kw)
         return L.prrp_batch_plan_create(a["count"], a["A"], a["n"], a["lda"], a["b"], a["perm"],
                                         a["stats"], a["tau"], a["schur"], a["rpw"], None, None,
-                                        None, None, 0.0, 0, ctypes.byref(h))
+                                        None, None, 0.0, 0, a.get("ws", None), a.get("wsb", 0),
+                                        None, ctypes.byref(h))
     assert call(count=0) == -1
     assert call(tau=1.0) == -8
     assert call(schur=3) == -9
     assert call(rpw=96) == -10
     assert call(b=(ctypes.c_int * 1)(9)) == -5       # b > n
     assert call(lda=(ctypes.c_int64 * 1)(4)) == -4   # lda < n
+    assert call() == -17                             # no workspace
+    assert call(ws=1, wsb=16) == -18                 # workspace too small
+    need = ctypes.c_size_t(0)
+    assert L.prrp_batch_plan_workspace_size(1, n8, b2, None, 64, ctypes.byref(need)) == 0
+    assert need.value > 8 * 8 * 2
+    need2 = ctypes.c_size_t(0)
+    nr = (ctypes.c_int64 * 1)(3)
+    assert L.prrp_batch_plan_workspace_size(1, n8, b2, nr, 64, ctypes.byref(need2)) == 0
+    assert need2.value > need.value                 # refinement needs solve workspace
+    assert L.prrp_batch_plan_workspace_size(1, n8, b2, None, 96, ctypes.byref(need)) == -5
     assert L.prrp_batch_plan_run(None, None, 0) == -1
     assert L.prrp_batch_plan_destroy(None) == 0
