@@ -94,6 +94,44 @@ def cpu_baseline(A_host, b, tau, panels):
             "seconds": dt}
 
 
+def serving_bench(nreq: int, seed: int):
+    """Continuous-batching solve server: n uniform in {64, 96, ..., 2048},
+    b = min(32, n/4), N(0,1) systems with 1-8 right-hand sides, FP32 Schur
+    update and FP64 refinement.  The autotuner picks the launch shapes, a
+    saturated run gives the capacity, and the Poisson run arrives at 0.7 of
+    it."""
+    import torch
+    from paper_1208_2451_amd import autotune, serving
+    t0 = time.perf_counter()
+    tuning = autotune.tune(batch=8, batch_options=(8, 16, 32), trials=1)
+    log("autotune %.1f s: %s" % (time.perf_counter() - t0, json.dumps(
+        {"rows_per_wg": tuning["rows_per_wg"], "max_batch": tuning["max_batch"]})))
+    rpw = autotune.rows_per_wg_fn(tuning)
+    srv = serving.Server(max_batch=tuning["max_batch"], slots=3, precision="fp32", max_iter=10,
+                         rows_per_wg=rpw)
+    warm = serving.materialize(serving.make_requests(24, seed + 5, 1e9), "cuda")
+    srv.serve(warm, realtime=False)
+    sat_reqs = serving.materialize(serving.make_requests(max(48, nreq // 2), seed + 1, 1e9), "cuda")
+    sat = srv.serve(sat_reqs, realtime=False)
+    log("serving saturated", json.dumps(sat))
+    rate = 0.7 * sat["solves_per_s"]
+    reqs = serving.materialize(serving.make_requests(nreq, seed + 2, rate), "cuda")
+    run = srv.serve(reqs, realtime=True)
+    torch.cuda.synchronize()
+    same = True
+    for r in reqs[:: max(1, len(reqs) // 8)]:
+        x, _ = serving.solve_alone(r, precision="fp32", max_iter=10, rows_per_wg=rpw(r.n))
+        same = same and bool(torch.equal(x, r.X))
+    run.update({"rate_per_s": rate, "saturated_solves_per_s": sat["solves_per_s"],
+                "saturated_tflops": sat["tflops"], "mix_equals_alone_sampled": same,
+                "max_batch": tuning["max_batch"], "rows_per_wg": tuning["rows_per_wg"],
+                "kind": "Poisson arrivals at 0.7 x saturated capacity; n uniform in {64..2048} "
+                        "step 32, b = min(32, n/4), 1-8 rhs, FP32 Schur + FP64 refinement to "
+                        "1e-14; latency = completion - arrival"})
+    del reqs, sat_reqs, warm
+    return run
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--solves", type=int, default=200)
+    ap.add_argument("--serving-requests", type=int, default=240,
+                    help="requests of the Poisson serving run (0 skips serving)")
     ap.add_argument("--host-matrix", action="store_true",
                     help="build the kappa matrix with NumPy on the host (same recipe) and copy it "
                          "in, instead of building it with device QR")
@@ -260,6 +300,11 @@ def main():
               "p99_ms": float(np.percentile(lat, 99)), "kind": "resident FP64 factors, n=%d, 1 rhs, "
               "one synchronized prrp_solve per request" % n}
 
+    serving_out = None
+    if args.serving_requests > 0:
+        log("serving: %d requests" % args.serving_requests)
+        serving_out = serving_bench(args.serving_requests, args.seed)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d panels" % args.cpu_panels)
@@ -279,6 +324,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "solves": solves,
+        "serving": serving_out,
     }
     print(json.dumps(out), flush=True)
 
