@@ -1,0 +1,130 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (look-ahead on, the library's default panel workgroups).
+
+* LU_PRRP FP64, n = 4096, b = 64: the whole oracle runs; permutation
+  identical, backward error <= 1e-15 n, growth equal to the oracle's and far
+  below GEPP's on the Wilkinson matrix (2^(n-1), Section 2.3) and the bound
+  (1 + tau b)^(n/b) (Section 2.2).
+* LU_PRRP FP64, n = 8192, b = 128 (the benchmark's matrix): the oracle's first
+  two panels fix the first 256 pivots, which must be identical; the backward
+  error is estimated on sampled rows of A[perm] - L U.
+* CALU_PRRP binary tree, n = 16384, b = 128, 512-row tiles: the oracle's first
+  two panels (32-leaf tournaments) fix the first 256 pivots; sampled backward
+  error; the tree height is 5; perm is a permutation; growth below the bound
+  ((1 + tau b)^((n/b)(H+1)), Section 3.2).
+* Mixed precision, n = 8192, kappa = 1e6: FP32-Schur factorization plus FP64
+  refinement reaches 1e-12 forward error against the reference solution (LAPACK
+  factors refined with the oracle's doubled-precision residual), 1 and 16
+  right-hand sides (two sampled columns of the 16 checked).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import lu as olu
+from oracle import solve as osolve
+from paper_1208_2451_amd import inputs
+from tests.gpu_util import announce, backward_error, gpu_factor
+
+pytestmark = pytest.mark.gpu
+
+
+def _sampled_backward_error(A, LU, perm, rows):
+    """sqrt(n/k sum_i ||(A[perm] - L U)_i||^2) / ||A||_F over k sampled rows."""
+    n = A.shape[0]
+    U = np.triu(LU)
+    tot = 0.0
+    for i in rows:
+        li = np.zeros(n)
+        li[:i] = LU[i, :i]
+        li[i] = 1.0
+        r = A[perm[i]] - li @ U
+        tot += float(r @ r)
+    return math.sqrt(tot * n / len(rows)) / np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("kind", ["randn", "wilkinson"])
+def test_lu_prrp_n4096_b64(kind):
+    n, b = 4096, 64
+    A = inputs.randn_system(n, 4096)[0] if kind == "randn" else inputs.wilkinson(n)
+    announce("full-size lu_prrp", kind, "n=%d b=%d" % (n, b))
+    LUg, permg, st, _, _ = gpu_factor(A, b)
+    f = olu.lu_prrp(A, b, 2.0)
+    assert st["info"] == 0
+    assert np.array_equal(permg, f.perm)
+    assert backward_error(A, LUg, permg) <= 1e-15 * n
+    assert st["g_W"] == pytest.approx(f.g_W, rel=1e-9)
+    log10_bound = (n / b) * math.log10(1 + 2.0 * b)           # 135.08
+    assert math.log10(st["g_W"]) < log10_bound
+    if kind == "wilkinson":
+        assert math.log10(st["g_W"]) < 0.01 * (n - 1) * math.log10(2.0)   # GEPP: 2^(n-1)
+    else:
+        lu_g, _ = sla.lu_factor(A)
+        g_gepp = np.abs(np.triu(lu_g)).max() / np.abs(A).max()
+        assert st["g_W"] < 100 * g_gepp
+
+
+def test_lu_prrp_n8192_b128_first_panels():
+    n, b = 8192, 128
+    A = inputs.kappa_matrix(n, 0, 1e6, device="cuda:0").cpu().numpy()
+    announce("full-size lu_prrp n=8192 b=128 (bench matrix)")
+    LUg, permg, st, _, _ = gpu_factor(A, b)
+    assert st["info"] == 0
+    assert np.array_equal(np.sort(permg), np.arange(n))
+    f2 = olu.lu_prrp(A, b, 2.0, panels=2)
+    assert np.array_equal(permg[:2 * b], f2.perm[:2 * b])
+    rows = np.random.default_rng(1).choice(n, 24, replace=False)
+    assert _sampled_backward_error(A, LUg, permg, rows) <= 1e-15 * n
+    assert st["max_block_L"] <= 2.0 * (1 + 2.0 ** -32)
+
+
+def test_calu_prrp_n16384_sampled():
+    n, b, tr = 16384, 128, 512
+    A = inputs.randn_system(n, 16384)[0]
+    announce("full-size calu_prrp n=16384 b=128 tiles=512 binary")
+    LUg, permg, st, _, _ = gpu_factor(A, b, method="calu", tree="binary", tile_rows=tr)
+    assert st["info"] == 0
+    assert st["tree_height"] == 5
+    assert np.array_equal(np.sort(permg), np.arange(n))
+    f2 = olu.calu_prrp(A, b, 2.0, tile_rows=tr, tree="binary", panels=2)
+    assert np.array_equal(permg[:2 * b], f2.perm[:2 * b])
+    rows = np.random.default_rng(2).choice(n, 16, replace=False)
+    assert _sampled_backward_error(A, LUg, permg, rows) <= 1e-15 * n
+    log10_bound = ((n / b) * (5 + 1) - 1) * math.log10(1 + 2.0 * b)
+    assert math.log10(st["g_W"]) < log10_bound
+
+
+@pytest.fixture(scope="module")
+def kappa8192():
+    n = 8192
+    A = inputs.kappa_matrix(n, 0, 1e6, device="cuda:0").cpu().numpy()
+    B = inputs.rhs(n, 0, 16)
+    lu_, piv = sla.lu_factor(A)
+    perm = np.arange(n)
+    for j, p in enumerate(piv):
+        perm[[j, p]] = perm[[p, j]]
+    cols = [0, 15]
+    x_ref = {c: osolve.refine(A, lu_, perm, B[:, c], tol=1e-16, max_iter=8)[0] for c in cols}
+    return A, B, x_ref
+
+
+@pytest.mark.parametrize("nrhs", [1, 16])
+def test_mixed_fp32_n8192_refined_to_1e12(kappa8192, nrhs):
+    import torch
+    import paper_1208_2451_amd as prrp
+    A, B, x_ref = kappa8192
+    announce("full-size mixed fp32 n=8192 nrhs=%d" % nrhs)
+    A0 = torch.from_numpy(A).cuda()
+    Af = A0.clone()
+    r = prrp.factor(Af, 128, 2.0, precision="fp32")
+    Bt = torch.from_numpy(np.ascontiguousarray(B[:, :nrhs])).cuda()
+    X, it, rel = prrp.refine(A0, Af, r.perm, Bt, tol=1e-14, max_iter=30)
+    torch.cuda.synchronize()
+    assert r.stats()["info"] == 0
+    Xh = X.cpu().numpy().reshape(A.shape[0], nrhs)
+    for c, xr in x_ref.items():
+        if c < nrhs:
+            err = np.abs(Xh[:, c] - xr).max() / np.abs(xr).max()
+            assert err <= 1e-12, (c, err, it)
