@@ -140,7 +140,7 @@ inline int herr(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
 
 // ------------------------------------------------ look-ahead side stream
 // The far part of each Schur update runs on a side stream whose CU mask
-// leaves PRRP_RESERVE_CUS (default 32) CUs free, so that the next panel's
+// leaves PRRP_RESERVE_CUS (default 64) CUs free, so that the next panel's
 // latency-bound kernels (strong RRQR, GEPP) on the caller's stream always
 // find free CUs and run concurrently with it.
 struct SideStream {
@@ -170,7 +170,7 @@ hipError_t side_stream(hipStream_t* out) {
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  int reserve = env ? atoi(env) : 32;
+  int reserve = env ? atoi(env) : 64;
   if (reserve < 0) reserve = 0;
   if (reserve > cus / 2) reserve = cus / 2;
   std::vector<uint32_t> mask((cus + 31) / 32, 0u);

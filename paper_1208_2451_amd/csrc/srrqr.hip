@@ -59,7 +59,8 @@ struct Smem {
   double* scal;    // [8]   beta, gamma, ...
   uint64_t* red;   // [16]  reduction scratch
   int* selpos;     // [kMaxB] tile positions in slot order
-  int* flags;      // [8]   0: abort, 1: rank deficient, 2: winner slot
+  int* flags;      // [8]   0: abort, 1: rank deficient, 2: winner slot,
+                   //       3: exchange slot, 4: failed wait of the key poll
 };
 
 }  // namespace
@@ -67,6 +68,14 @@ struct Smem {
 size_t srrqr_smem_bytes(int bw) {
   return sizeof(double) * (size_t)(bw * (bw + 1) / 2 + 4 * kMaxB + 8) + sizeof(uint64_t) * 16 +
          sizeof(int) * (kMaxB + 8);
+}
+
+// Words a post of a panel of width bw may have written: key, slot and the
+// row in whole blocks of 8 columns per lane (CPT rounded as in dispatch).
+__device__ __forceinline__ int post_width(int bw) {
+  int cpt = (bw + 7) / 8;
+  cpt = cpt <= 2 ? (cpt <= 1 ? 1 : 2) : (cpt <= 4 ? 4 : (cpt <= 8 ? 8 : 16));
+  return 2 + 8 * cpt;
 }
 
 template <int CPT, int RPT>
@@ -128,7 +137,7 @@ void srrqr_kernel(SrrqrArgs a) {
     if (P.clear_base != nullptr) {
       const int nthr = G * kThreads;
       const int gt = w * kThreads + tid;
-      const int per_post = 2 + P.clear_bw;
+      const int per_post = post_width(P.clear_bw);
       const size_t total = (size_t)(*P.clear_rounds) * P.clear_G * per_post;
       for (size_t e = gt; e < total; e += nthr) {
         const size_t post = e / per_post;
@@ -139,7 +148,7 @@ void srrqr_kernel(SrrqrArgs a) {
   } else if (a.clear_base != nullptr) {
     const int nthr = gridDim.x * kThreads;
     const int gt = blockIdx.x * kThreads + tid;
-    const int per_post = 2 + a.clear_bw;
+    const int per_post = post_width(a.clear_bw);
     for (int cg = 0; cg < a.clear_ngroups; ++cg) {
       const int used = a.clear_rounds[cg];
       uint64_t* base = a.clear_base + (size_t)cg * a.clear_group_stride;
@@ -251,23 +260,37 @@ void srrqr_kernel(SrrqrArgs a) {
       uint64_t gkey = wkey;
       uint64_t* post_r = slots + (size_t)s * round_stride;
       if (multi) {
-        // post my candidate: the owner's 8 lanes write the row, then the key
+        // post my candidate: the owner's 8 lanes write the row (all 8 CPT
+        // words fit the post's width; words past bw are never read), then the key
+        int cq = -1;
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          if (wkey != 0 && live[q] && !chosen[q] && (uint32_t)tpos[q] == key_index(wkey)) {
+        for (int q = 0; q < RPT; ++q)
+          if (wkey != 0 && live[q] && !chosen[q] && (uint32_t)tpos[q] == key_index(wkey)) cq = q;
+        if (cq >= 0) {
+          double xv[CPT];
 #pragma unroll
-            for (int k = 0; k < CPT; ++k) {
-              const int c = l8 + 8 * k;
-              if (c < bw)
-                st_dev(post_r + (size_t)w * kPostW + 2 + c, (uint64_t)__double_as_longlong(x[q][k]));
-            }
+          for (int k = 0; k < CPT; ++k) {
+            xv[k] = x[0][k];
+#pragma unroll
+            for (int q = 1; q < RPT; ++q) xv[k] = (cq == q) ? x[q][k] : xv[k];
           }
+          uint64_t* dst = post_r + (size_t)w * kPostW + 2 + l8;
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) st_dev(dst + 8 * k, (uint64_t)__double_as_longlong(xv[k]));
         }
         if (tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
-        // every wave polls all G keys
-        uint64_t kv = 0;
-        for (int m = lane; m < G; m += 64) kv = umax(kv, poll_word(post_r + (size_t)m * kPostW, a.abort_flag, &wbad));
-        gkey = wave_max_key(kv);
+        // wave 0 polls the G keys (one poller per workgroup keeps the fabric
+        // traffic low) and shares the maximum through LDS
+        if (wave == 0) {
+          uint64_t kv = 0;
+          for (int m = lane; m < G; m += 64)
+            kv = umax(kv, poll_word(post_r + (size_t)m * kPostW, a.abort_flag, &wbad));
+          kv = wave_max_key(kv);
+          if (lane == 0) { S.red[8] = kv; S.flags[4] = wbad; }
+        }
+        __syncthreads();
+        gkey = S.red[8];
+        wbad = S.flags[4];
       }
       if (gkey == 0 && !wbad) {      // fewer rows than columns: not a valid tile
         if (tid == 0) set_info(pst, -2);
