@@ -99,7 +99,8 @@ int groups_for_rows(int64_t rows, int cap, int target = 64) {
 struct Layout {
   size_t slots_set_words = 0;     // words per slot set
   size_t off_slots = 0, off_rounds = 0, off_abort = 0, off_sel = 0, off_lists = 0;
-  size_t off_y = 0, off_pl = 0, off_linv = 0, off_moves = 0, off_lsel = 0;
+  size_t off_y = 0, off_pl = 0, off_p11 = 0, off_moves = 0, off_lsel = 0;
+  size_t y_stride = 0, sel_stride = 0;   // the two panels' Y and sel buffers
   size_t total = 0;
   int max_members = 0;            // sum over groups of workgroups in any launch
   int max_groups = 0;
@@ -125,12 +126,14 @@ Layout make_layout(int64_t n, int b, int method, int64_t tile_rows) {
   L.off_slots = off;  off += align_up(2 * L.slots_set_words * 8, 256);
   L.off_rounds = off; off += align_up(2 * (size_t)groups * 4 + 16, 256);
   L.off_abort = off;  off += 256;
-  L.off_sel = off;    off += align_up((size_t)groups * kMaxB * 4, 256);
+  L.off_sel = off;    off += align_up((size_t)2 * groups * kMaxB * 4, 256);   // two panels
   L.off_lsel = off;   off += align_up((size_t)2 * groups * kMaxB * 4, 256);
   L.off_lists = off;  off += align_up((size_t)groups * (2 * kMaxB + (size_t)tile_rows + 64) * 4 + 64, 256);
-  L.off_y = off;      off += align_up((size_t)n * b * 8, 256);
+  L.off_y = off;      off += 2 * align_up((size_t)n * b * 8, 256);         // two panels
+  L.y_stride = align_up((size_t)n * b * 8, 256);
+  L.sel_stride = (size_t)groups * kMaxB;
   L.off_pl = off;     off += align_up((size_t)b * b * 8, 256);
-  L.off_linv = off;   off += align_up((size_t)b * b * 8, 256);
+  L.off_p11 = off;    off += align_up((size_t)kMaxB * 4, 256);
   L.off_moves = off;  off += align_up((size_t)(4 * kMaxB + 4) * 4, 256);
   L.total = off;
   return L;
@@ -147,7 +150,8 @@ struct SideStream {
   int dev = -1;
   hipStream_t s = nullptr;
   hipStream_t main = nullptr;   // non-blocking stream carrying the panel chain
-  hipEvent_t ev[8] = {};
+  hipStream_t s2 = nullptr;     // GEPP / L21 / U12 of finished panels
+  hipEvent_t ev[64] = {};
   int next = 0;
 };
 SideStream g_side;
@@ -187,6 +191,8 @@ hipError_t side_stream(hipStream_t* out) {
   }
   e = hipStreamCreateWithFlags(&g_side.main, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
+  e = hipStreamCreateWithFlags(&g_side.s2, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
   g_side.s = s;
   g_side.dev = dev;
   *out = s;
@@ -195,7 +201,7 @@ hipError_t side_stream(hipStream_t* out) {
 
 hipEvent_t side_event() {
   hipEvent_t e = g_side.ev[g_side.next];
-  g_side.next = (g_side.next + 1) & 7;
+  g_side.next = (g_side.next + 1) & 63;
   return e;
 }
 
@@ -267,7 +273,10 @@ struct Ctx {
   int cap = 256;
   int rpw_target = 64;               // rows per panel workgroup (64 or 128)
   hipStream_t side = nullptr;        // look-ahead stream (null: no look-ahead)
+  hipStream_t side2 = nullptr;       // GEPP / L21 / U12 stream (null: no look-ahead)
   hipEvent_t far_event = nullptr;    // pending far Schur update on `side`
+  hipEvent_t l21_event = nullptr;    // pending L21 of the previous panel on `side2`
+  int pidx = 0;                      // panel index (parity of sel / Y)
 
   uint64_t* slot_set(int parity) {
     return reinterpret_cast<uint64_t*>(ws + L.off_slots) + (size_t)parity * L.slots_set_words;
@@ -276,12 +285,16 @@ struct Ctx {
     return reinterpret_cast<int32_t*>(ws + L.off_rounds) + (size_t)parity * L.max_groups;
   }
   uint32_t* abort_flag() { return reinterpret_cast<uint32_t*>(ws + L.off_abort); }
-  int32_t* sel() { return reinterpret_cast<int32_t*>(ws + L.off_sel); }
+  // sel and Y alternate between panels: the next panel's strong RRQR writes
+  // one pair while the previous panel's GEPP, L21 and far update read the other
+  int32_t* sel() {
+    return reinterpret_cast<int32_t*>(ws + L.off_sel) + (size_t)(pidx & 1) * L.sel_stride;
+  }
   int32_t* lsel() { return reinterpret_cast<int32_t*>(ws + L.off_lsel); }
   int32_t* lists() { return reinterpret_cast<int32_t*>(ws + L.off_lists); }
-  double* Y() { return reinterpret_cast<double*>(ws + L.off_y); }
+  double* Y() { return reinterpret_cast<double*>(ws + L.off_y + (size_t)(pidx & 1) * L.y_stride); }
   double* PL() { return reinterpret_cast<double*>(ws + L.off_pl); }
-  double* Linv() { return reinterpret_cast<double*>(ws + L.off_linv); }
+  int32_t* p11() { return reinterpret_cast<int32_t*>(ws + L.off_p11); }
   int32_t* mv() { return reinterpret_cast<int32_t*>(ws + L.off_moves); }
 
   // One srrqr launch; fills in the slot-set bookkeeping.
@@ -315,78 +328,130 @@ struct Ctx {
   }
 
   // Steps after the pivot rows of the panel at k0 are known (sel(), Y()).
+  //
+  // Critical path (stream st): the moves of Pi_j, then the trailing update in
+  // the block form of Algorithm "LU_PRRP factorization", A22 -= L_2j A12 with
+  // L_2j = M^T (Y) and A12 before the diagonal GEPP, which is all the next
+  // panel needs.  Off the critical path (side2): GEPP of the diagonal block,
+  // Pi11 on the left columns and perm, the stored L21 = M^T Pi11 L11 and
+  // U12 = L11^-1 Pi11^T A12 (after both parts of the trailing update have
+  // read A12).  The far part of the update runs on `side`.
   hipError_t finish_panel(int64_t k0, int bw) {
     const int64_t m = n - k0;
     int32_t* mv_dst = mv();
     int32_t* mv_src = mv() + 2 * kMaxB;
     int32_t* n_moves = mv() + 4 * kMaxB;
-    GeppArgs ga{A, lda, k0, bw, (int)m, sel(), PL(), mv_dst, mv_src, n_moves, stats};
+    double* Yp = Y();
+    GeppArgs ga{A, lda, k0, bw, (int)m, sel(), PL(), mv_dst, mv_src, n_moves, stats, p11()};
     hipError_t e;
     {
-      PhaseScope ps(1, st);
-      e = launch_gepp(ga, st);
+      PhaseScope ps(2, st);
+      e = launch_plan(ga, st);
     }
     if (e != hipSuccess) return e;
+    // rows may move once the previous far update and L21 have landed
     if (far_event != nullptr) {
       e = hipStreamWaitEvent(st, far_event, 0);
       if (e != hipSuccess) return e;
       far_event = nullptr;
     }
-    MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, (m > bw) ? Y() : nullptr, b};
+    if (l21_event != nullptr) {
+      e = hipStreamWaitEvent(st, l21_event, 0);
+      if (e != hipSuccess) return e;
+      l21_event = nullptr;
+    }
+    MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, (m > bw) ? Yp : nullptr, b};
     {
       PhaseScope ps(2, st);
       e = launch_moves(ma, st);
     }
     if (e != hipSuccess) return e;
+    hipStream_t gs = (side2 != nullptr) ? side2 : st;
+    hipEvent_t ev_moved = nullptr, ev_near = nullptr, ev_far = nullptr;
+    if (side2 != nullptr) {
+      ev_moved = side_event();
+      e = hipEventRecord(ev_moved, st);
+      if (e != hipSuccess) return e;
+    }
+    const int64_t nr = n - k0 - bw;
+    double* a12 = A + k0 * lda + k0 + bw;
     if (m > bw) {
-      // L21 = M^T (Pi11 L11)
-      GemmArgs l21{(int)(m - bw), bw, bw, Y() + (size_t)bw * b, b, PL(), bw,
-                   A + (k0 + bw) * lda + k0, lda, 1.0, 0.0, nullptr, nullptr, PRRP_FP64};
-      {
-        PhaseScope ps(3, st);
-        e = launch_gemm(l21, st);
-      }
-      if (e != hipSuccess) return e;
-      const int64_t nr = n - k0 - bw;
-      double* a12 = A + k0 * lda + k0 + bw;
-      {
-        PhaseScope ps(4, st);
-        e = launch_trsm_u12(A, lda, k0, bw, nr, &stats->max_abs_U, &stats->max_abs_W, st);
-      }
-      if (e != hipSuccess) return e;
-      // Schur update: the next panel's columns on this stream, the rest on
-      // the side stream (look-ahead) or here
-      const int64_t n_near = (side != nullptr) ? std::min<int64_t>(b, nr) : nr;
-      double* l21p = A + (k0 + bw) * lda + k0;
+      // trailing update A22 -= M^T A12 (block form): the next panel's columns
+      // here, the rest on the side stream (look-ahead) or here
+      const double* yrest = Yp + (size_t)bw * b;
       double* a22 = A + (k0 + bw) * lda + k0 + bw;
-      hipEvent_t e_u12 = nullptr;
-      if (side != nullptr && nr > n_near) {
-        e_u12 = side_event();
-        e = hipEventRecord(e_u12, st);
-        if (e != hipSuccess) return e;
-      }
-      GemmArgs sc{(int)(m - bw), (int)n_near, bw, l21p, lda, a12, lda, a22, lda, -1.0, 1.0,
+      const int64_t n_near = (side != nullptr) ? std::min<int64_t>(b, nr) : nr;
+      GemmArgs sc{(int)(m - bw), (int)n_near, bw, yrest, b, a12, lda, a22, lda, -1.0, 1.0,
                   &stats->max_abs_W, nullptr, schur};
       {
         PhaseScope ps(5, st);
         e = launch_gemm(sc, st);
       }
       if (e != hipSuccess) return e;
-      if (e_u12 != nullptr) {
-        e = hipStreamWaitEvent(side, e_u12, 0);
+      if (side2 != nullptr) {
+        ev_near = side_event();
+        e = hipEventRecord(ev_near, st);
         if (e != hipSuccess) return e;
-        GemmArgs sc_far{(int)(m - bw), (int)(nr - n_near), bw, l21p, lda, a12 + n_near, lda,
+      }
+      if (side != nullptr && nr > n_near) {
+        e = hipStreamWaitEvent(side, ev_moved, 0);
+        if (e != hipSuccess) return e;
+        GemmArgs sc_far{(int)(m - bw), (int)(nr - n_near), bw, yrest, b, a12 + n_near, lda,
                         a22 + n_near, lda, -1.0, 1.0, &stats->max_abs_W, nullptr, schur};
         {
           PhaseScope ps(5, side);
           e = launch_gemm(sc_far, side);
         }
         if (e != hipSuccess) return e;
-        far_event = side_event();
-        e = hipEventRecord(far_event, side);
+        ev_far = side_event();
+        e = hipEventRecord(ev_far, side);
         if (e != hipSuccess) return e;
+        far_event = ev_far;
       }
     }
+    // ---- GEPP path
+    if (side2 != nullptr) {
+      e = hipStreamWaitEvent(gs, ev_moved, 0);
+      if (e != hipSuccess) return e;
+    }
+    {
+      PhaseScope ps(1, gs);
+      e = launch_gepp(ga, gs);
+    }
+    if (e != hipSuccess) return e;
+    PermTopArgs pt{A, lda, k0, bw, perm, p11()};
+    {
+      PhaseScope ps(1, gs);
+      e = launch_perm_top(pt, gs);
+    }
+    if (e != hipSuccess) return e;
+    if (m > bw) {
+      // L21 = M^T (Pi11 L11)
+      GemmArgs l21{(int)(m - bw), bw, bw, Yp + (size_t)bw * b, b, PL(), bw,
+                   A + (k0 + bw) * lda + k0, lda, 1.0, 0.0, nullptr, nullptr, PRRP_FP64};
+      {
+        PhaseScope ps(3, gs);
+        e = launch_gemm(l21, gs);
+      }
+      if (e != hipSuccess) return e;
+      if (side2 != nullptr) {
+        l21_event = side_event();
+        e = hipEventRecord(l21_event, gs);
+        if (e != hipSuccess) return e;
+        e = hipStreamWaitEvent(gs, ev_near, 0);
+        if (e != hipSuccess) return e;
+        if (ev_far != nullptr) {
+          e = hipStreamWaitEvent(gs, ev_far, 0);
+          if (e != hipSuccess) return e;
+        }
+      }
+      {
+        PhaseScope ps(4, gs);
+        e = launch_trsm_u12(A, lda, k0, bw, nr, &stats->max_abs_U, &stats->max_abs_W, p11(), gs);
+      }
+      if (e != hipSuccess) return e;
+    }
+    ++pidx;
     return hipSuccess;
   }
 };
@@ -438,7 +503,9 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
     PRRP_TRY(hipEventRecord(e0, caller));
     PRRP_TRY(hipStreamWaitEvent(c.side, e0, 0));
     PRRP_TRY(hipStreamWaitEvent(g_side.main, e0, 0));
+    PRRP_TRY(hipStreamWaitEvent(g_side.s2, e0, 0));
     c.st = g_side.main;
+    c.side2 = g_side.s2;
   }
   int height = 0;
   if (method == 1) {
@@ -552,6 +619,11 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
     PRRP_TRY(c.finish_panel(k0, bw));
   }
   if (c.far_event != nullptr) PRRP_TRY(hipStreamWaitEvent(c.st, c.far_event, 0));
+  if (c.side2 != nullptr) {
+    hipEvent_t e2 = side_event();
+    PRRP_TRY(hipEventRecord(e2, c.side2));
+    PRRP_TRY(hipStreamWaitEvent(c.st, e2, 0));
+  }
   if (c.st != caller) {
     hipEvent_t e1 = side_event();
     PRRP_TRY(hipEventRecord(e1, c.st));
@@ -848,7 +920,7 @@ struct PlanProblem {
   prrp_stats* stats;
   int Gmax;
   size_t set_words;
-  size_t off_slots, off_rounds, off_sel, off_y, off_pl, off_mv, off_sws;
+  size_t off_slots, off_rounds, off_sel, off_y, off_pl, off_mv, off_sws, off_p11;
   // refinement (A0 == nullptr: none)
   const double* A0;
   const double* B;
@@ -858,7 +930,7 @@ struct PlanProblem {
   size_t sws_bytes;
 };
 
-enum OpKind { OP_SRRQR = 0, OP_GEPP, OP_MOVES, OP_L21, OP_U12, OP_SCHUR };
+enum OpKind { OP_SRRQR = 0, OP_PLAN, OP_MOVES, OP_SCHUR, OP_GEPP, OP_PERMTOP, OP_L21, OP_U12 };
 struct PlanOp {
   OpKind kind;
   size_t off;          // byte offset of the work list in the workspace
@@ -938,6 +1010,7 @@ void plan_build(BatchPlan& P) {
     q.off_y = take((size_t)q.n * q.b * 8);
     q.off_pl = take((size_t)q.b * q.b * 8);
     q.off_mv = take((4 * kMaxB + 4) * 4);
+    q.off_p11 = take(kMaxB * 4);
     q.off_sws = 0;
     if (P.refine) {
       prrp_solve_workspace_size(q.n, q.nrhs, &q.sws_bytes);
@@ -1024,8 +1097,9 @@ void plan_build(BatchPlan& P) {
     std::vector<MoveArgs> ml;
     std::vector<GemmArgs> l21, sch;
     std::vector<TrsmArgs> tl;
+    std::vector<PermTopArgs> pl;
     int maxbw = 0;
-    int64_t maxout = 0, maxm2 = 0, maxnr = 0;
+    int64_t maxout = 0, maxm2 = 0, maxnr = 0, maxk0 = 0;
     for (int64_t i = 0; i < count; ++i) {
       const PlanProblem& q = P.p[i];
       const int64_t k0 = s * q.b;
@@ -1033,42 +1107,52 @@ void plan_build(BatchPlan& P) {
       const int64_t m = q.n - k0;
       const int bw = (int)std::min<int64_t>(q.b, m);
       maxbw = std::max(maxbw, bw);
+      maxk0 = std::max(maxk0, k0);
       int32_t* mv_dst = reinterpret_cast<int32_t*>(W(q.off_mv));
       int32_t* mv_src = reinterpret_cast<int32_t*>(W(q.off_mv + 2 * kMaxB * 4));
       int32_t* n_moves = reinterpret_cast<int32_t*>(W(q.off_mv + 4 * kMaxB * 4));
+      int32_t* p11 = reinterpret_cast<int32_t*>(W(q.off_p11));
       double* Yp = reinterpret_cast<double*>(W(q.off_y));
       double* PLp = reinterpret_cast<double*>(W(q.off_pl));
       gl.push_back(GeppArgs{q.A, q.lda, k0, bw, (int)m, reinterpret_cast<int32_t*>(W(q.off_sel)),
-                            PLp, mv_dst, mv_src, n_moves, q.stats});
+                            PLp, mv_dst, mv_src, n_moves, q.stats, p11});
       ml.push_back(MoveArgs{q.A, q.lda, q.n, k0, bw, mv_dst, mv_src, n_moves, q.perm,
                             (m > bw) ? Yp : nullptr, q.b});
+      pl.push_back(PermTopArgs{q.A, q.lda, k0, bw, q.perm, p11});
       maxout = std::max<int64_t>(maxout, q.n - bw);
       if (m > bw) {
         const int64_t nr = q.n - k0 - bw;
-        // Y rows from bw on: offset of Y plus bw rows of ld b
+        // M^T rows from bw on: offset of Y plus bw rows of ld b
         double* Yrows = reinterpret_cast<double*>(W(q.off_y + (size_t)bw * q.b * 8));
+        // block form A22 -= M^T A12 (A12 before the diagonal GEPP)
+        sch.push_back(GemmArgs{(int)(m - bw), (int)nr, bw, Yrows, q.b,
+                               q.A + k0 * q.lda + k0 + bw, q.lda, q.A + (k0 + bw) * q.lda + k0 + bw,
+                               q.lda, -1.0, 1.0, &q.stats->max_abs_W, nullptr, P.schur});
         l21.push_back(GemmArgs{(int)(m - bw), bw, bw, Yrows, q.b, PLp, bw,
                                q.A + (k0 + bw) * q.lda + k0, q.lda, 1.0, 0.0, nullptr, nullptr,
                                PRRP_FP64});
-        tl.push_back(TrsmArgs{q.A, q.lda, k0, bw, nr, &q.stats->max_abs_U, &q.stats->max_abs_W});
-        sch.push_back(GemmArgs{(int)(m - bw), (int)nr, bw, q.A + (k0 + bw) * q.lda + k0, q.lda,
-                               q.A + k0 * q.lda + k0 + bw, q.lda, q.A + (k0 + bw) * q.lda + k0 + bw,
-                               q.lda, -1.0, 1.0, &q.stats->max_abs_W, nullptr, P.schur});
+        tl.push_back(TrsmArgs{q.A, q.lda, k0, bw, nr, &q.stats->max_abs_U, &q.stats->max_abs_W,
+                              p11});
         maxm2 = std::max<int64_t>(maxm2, m - bw);
         maxnr = std::max<int64_t>(maxnr, nr);
       }
     }
-    P.ops.push_back(PlanOp{OP_GEPP, put(gl.data(), gl.size() * sizeof(GeppArgs)), (int)gl.size(),
+    P.ops.push_back(PlanOp{OP_PLAN, put(gl.data(), gl.size() * sizeof(GeppArgs)), (int)gl.size(),
                            maxbw, 0, 0, 0, -1});
     P.ops.push_back(PlanOp{OP_MOVES, put(ml.data(), ml.size() * sizeof(MoveArgs)), (int)ml.size(),
                            maxbw, maxout, 0, 0, -1});
+    if (!sch.empty())
+      P.ops.push_back(PlanOp{OP_SCHUR, put(sch.data(), sch.size() * sizeof(GemmArgs)),
+                             (int)sch.size(), maxbw, maxm2, maxnr, P.schur, -1});
+    P.ops.push_back(PlanOp{OP_GEPP, put(gl.data(), gl.size() * sizeof(GeppArgs)), (int)gl.size(),
+                           maxbw, 0, 0, 0, -1});
+    P.ops.push_back(PlanOp{OP_PERMTOP, put(pl.data(), pl.size() * sizeof(PermTopArgs)),
+                           (int)pl.size(), maxbw, maxk0, 0, 0, -1});
     if (!l21.empty()) {
       P.ops.push_back(PlanOp{OP_L21, put(l21.data(), l21.size() * sizeof(GemmArgs)),
                              (int)l21.size(), maxbw, maxm2, maxbw, PRRP_FP64, -1});
       P.ops.push_back(PlanOp{OP_U12, put(tl.data(), tl.size() * sizeof(TrsmArgs)), (int)tl.size(),
                              maxbw, maxnr, 0, 0, -1});
-      P.ops.push_back(PlanOp{OP_SCHUR, put(sch.data(), sch.size() * sizeof(GemmArgs)),
-                             (int)sch.size(), maxbw, maxm2, maxnr, P.schur, -1});
     }
   }
   P.need = P.lists_at + host.size();
@@ -1094,10 +1178,10 @@ void plan_relocate(BatchPlan& P) {
   }
   for (PlanOp& o : P.ops) {
     char* h = P.host.data() + o.off;
-    if (o.kind == OP_GEPP) {
+    if (o.kind == OP_GEPP || o.kind == OP_PLAN) {
       GeppArgs* g = reinterpret_cast<GeppArgs*>(h);
       for (int k = 0; k < o.count; ++k) {
-        R(g[k].sel); R(g[k].PL); R(g[k].mv_dst); R(g[k].mv_src); R(g[k].n_moves);
+        R(g[k].sel); R(g[k].PL); R(g[k].mv_dst); R(g[k].mv_src); R(g[k].n_moves); R(g[k].p11);
       }
     } else if (o.kind == OP_MOVES) {
       MoveArgs* m = reinterpret_cast<MoveArgs*>(h);
@@ -1105,6 +1189,15 @@ void plan_relocate(BatchPlan& P) {
     } else if (o.kind == OP_L21) {
       GemmArgs* g = reinterpret_cast<GemmArgs*>(h);
       for (int k = 0; k < o.count; ++k) { R(g[k].A); R(g[k].B); }
+    } else if (o.kind == OP_SCHUR) {
+      GemmArgs* g = reinterpret_cast<GemmArgs*>(h);
+      for (int k = 0; k < o.count; ++k) R(g[k].A);
+    } else if (o.kind == OP_PERMTOP) {
+      PermTopArgs* t = reinterpret_cast<PermTopArgs*>(h);
+      for (int k = 0; k < o.count; ++k) R(t[k].p11);
+    } else if (o.kind == OP_U12) {
+      TrsmArgs* t = reinterpret_cast<TrsmArgs*>(h);
+      for (int k = 0; k < o.count; ++k) R(t[k].p11);
     }
     o.off += P.lists_at;
   }
@@ -1127,7 +1220,11 @@ hipError_t plan_enqueue(BatchPlan& P, hipStream_t st) {
     char* list = P.base + o.off;
     switch (o.kind) {
       case OP_SRRQR: e = launch_srrqr(P.srrqr_args[o.srrqr_index], st); break;
+      case OP_PLAN: e = launch_plan_batched(reinterpret_cast<GeppArgs*>(list), o.count, st); break;
       case OP_GEPP: e = launch_gepp_batched(reinterpret_cast<GeppArgs*>(list), o.count, o.bw, st); break;
+      case OP_PERMTOP:
+        e = launch_perm_top_batched(reinterpret_cast<PermTopArgs*>(list), o.count, o.max_a, st);
+        break;
       case OP_MOVES:
         e = launch_moves_batched(reinterpret_cast<MoveArgs*>(list), o.count, o.max_a, st);
         break;

@@ -1,24 +1,26 @@
 // Diagonal-block GEPP and row interchanges of one LU_PRRP panel step.
 //
-// Algorithm "LU_PRRP factorization", lines applying Pi_j^T to the entire
-// matrix and factoring the b x b diagonal block with partial pivoting
-// (A_jj = Pi_jj L_jj U_jj), Section 2.1.
+// Algorithm "LU_PRRP factorization", Section 2.1: Pi_j^T applied to the
+// entire matrix, the b x b diagonal block factored with partial pivoting
+// (A_jj = Pi_jj L_jj U_jj), and the point form of L and U12.
 //
-// gepp_kernel (one workgroup):
-//   1. plan: Pi_j^T as the transpositions "row k0+i <-> current position of
-//      the i-th selected row" (i = 0..bw-1), reduced to a list of whole-row
-//      moves (destination position <- source row);
-//   2. GEPP of the gathered block (selected rows in slot order) with the tie
-//      rule, blocked by 8 columns: one wave factors each 8-column sub-panel in
-//      registers (rows keep their slots; only their position labels move),
-//      the block's interchanges and U block are applied column-parallel, and
-//      a rank-8 update follows; the interchanges are folded into the moves of
-//      the top bw rows;
-//   3. outputs: L11\U11 written into A's diagonal block and PL = Pi11 L11 (so
-//      that L21 = M^T PL, the point form of the block L = (R11^-1 R12)^T).
+// plan_kernel (one wave): Pi_j^T as the transpositions "row k0+i <-> current
+//   position of the i-th selected row" (i = 0..bw-1), reduced to a list of
+//   whole-row moves (destination position <- source row).
 // moves_kernel: applies the moves to the columns outside the panel, to perm,
-// and to the rows of M^T that belong to displaced rows.
-// trsm_u12_kernel: U12 = L11^-1 A12 (after the moves), column-parallel.
+//   and to the rows of M^T that belong to displaced rows.
+// gepp_kernel (one workgroup): gathers the selected rows' panel block (in
+//   slot order, from their positions before the moves) and factors it with
+//   the tie rule, blocked by 8 columns: one wave factors each 8-column
+//   sub-panel in registers (rows keep their slots; only their position labels
+//   move), the block's interchanges and U block are applied column-parallel,
+//   and a rank-8 update follows.  Outputs: L11\U11 in A's diagonal block,
+//   PL = Pi11 L11 (so that L21 = M^T PL, the point form of the block
+//   L = (R11^-1 R12)^T), and p11 (the slot at each final position).
+// perm_top_kernel: applies Pi11 to the top bw rows in the columns left of the
+//   panel and to perm.
+// trsm_u12_kernel: U12 = L11^-1 Pi11^T A12, column-parallel (A12 rows read in
+//   Pi11 order, written back in place).
 #include "common.h"
 #include "kernels.h"
 
@@ -49,11 +51,7 @@ __device__ __forceinline__ void gepp_body(const GeppArgs& a) {
   double* D = sm;                               // [bw][ld]
   int* ssel = reinterpret_cast<int*>(D + bw * ld);   // [kMaxB] selection, slot order
   int* p11 = ssel + kMaxB;                      // [kMaxB] slot at each final position
-  int* topAt = p11 + kMaxB;                     // [kMaxB] plan: panel row at top position
-  int* dstq = topAt + kMaxB;                    // [kMaxB] plan: displaced destinations
-  int* dsrc = dstq + kMaxB;                     // [kMaxB] plan: displaced sources
-  int* ipivb = dsrc + kMaxB;                    // [8] interchanges of the current block
-  int* misc = ipivb + 8;                        // [8]
+  int* ipivb = p11 + kMaxB;                     // [8] interchanges of the current block
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
 
@@ -83,41 +81,6 @@ __device__ __forceinline__ void gepp_body(const GeppArgs& a) {
         const int i = ty + 16 * u, c = tx + 16 * w;
         if (i < bw && c < bw) D[i * ld + c] = v[u][w];
       }
-  }
-  // transposition plan, one wave in registers
-  if (wave == 0) {
-    LaneArr top{lane, lane + 64}, pos{lane, lane + 64}, rec{0, 0}, dq{0, 0}, ds{0, 0};
-    int nd = 0;
-    for (int i = 0; i < bw; ++i) {
-      const int r = __builtin_amdgcn_readfirstlane(ssel[i]);
-      const int q = (r < bw) ? pos.get(r) : r;
-      if (q == i) continue;
-      const int d = top.get(i);
-      top.set(i, r, lane);
-      if (r < bw) pos.set(r, i, lane);
-      if (q < bw) {
-        top.set(q, d, lane);
-        pos.set(d, q, lane);
-      } else {
-        int k;
-        if (r < bw) {
-          k = rec.get(r);
-        } else {
-          k = nd++;
-          dq.set(k, q, lane);
-        }
-        ds.set(k, d, lane);
-        rec.set(d, k, lane);
-        pos.set(d, q, lane);
-      }
-    }
-    topAt[lane] = top.lo;
-    topAt[lane + 64] = top.hi;
-    dstq[lane] = dq.lo;
-    dstq[lane + 64] = dq.hi;
-    dsrc[lane] = ds.lo;
-    dsrc[lane + 64] = ds.hi;
-    if (lane == 0) misc[0] = nd;
   }
   __syncthreads();
 
@@ -268,16 +231,7 @@ __device__ __forceinline__ void gepp_body(const GeppArgs& a) {
       a.PL[p11[i] * bw + c] = (c < i) ? v : (c == i ? 1.0 : 0.0);
     }
   }
-  if (tid < bw) {
-    a.mv_dst[tid] = tid;
-    a.mv_src[tid] = topAt[p11[tid]];
-  }
-  const int nd = misc[0];
-  if (tid < nd) {
-    a.mv_dst[bw + tid] = dstq[tid];
-    a.mv_src[bw + tid] = dsrc[tid];
-  }
-  if (tid == 0) *a.n_moves = bw + nd;
+  if (tid < bw) a.p11[tid] = p11[tid];
   if (a.stats) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) umax = fmax(umax, __shfl_xor(umax, o, 64));
@@ -286,6 +240,107 @@ __device__ __forceinline__ void gepp_body(const GeppArgs& a) {
       atomic_max_pos(&a.stats->max_abs_W, umax);
     }
   }
+}
+
+// Moves of Pi_j^T (one wave; plan in registers).
+__device__ __forceinline__ void plan_body(const GeppArgs& a) {
+  __shared__ int ssel[kMaxB];
+  const int bw = a.bw;
+  const int lane = threadIdx.x;
+  ssel[lane] = lane < bw ? a.sel[lane] : 0;
+  ssel[lane + 64] = lane + 64 < bw ? a.sel[lane + 64] : 0;
+  __syncthreads();
+  LaneArr top{lane, lane + 64}, pos{lane, lane + 64}, rec{0, 0}, dq{0, 0}, ds{0, 0};
+  int nd = 0;
+  for (int i = 0; i < bw; ++i) {
+    const int r = __builtin_amdgcn_readfirstlane(ssel[i]);
+    const int q = (r < bw) ? pos.get(r) : r;
+    if (q == i) continue;
+    const int d = top.get(i);
+    top.set(i, r, lane);
+    if (r < bw) pos.set(r, i, lane);
+    if (q < bw) {
+      top.set(q, d, lane);
+      pos.set(d, q, lane);
+    } else {
+      int k;
+      if (r < bw) {
+        k = rec.get(r);
+      } else {
+        k = nd++;
+        dq.set(k, q, lane);
+      }
+      ds.set(k, d, lane);
+      rec.set(d, k, lane);
+      pos.set(d, q, lane);
+    }
+  }
+  // top positions take the selected rows in slot order
+  if (lane < bw) { a.mv_dst[lane] = lane; a.mv_src[lane] = top.lo; }
+  if (lane + 64 < bw) { a.mv_dst[lane + 64] = lane + 64; a.mv_src[lane + 64] = top.hi; }
+  if (lane < nd) { a.mv_dst[bw + lane] = dq.lo; a.mv_src[bw + lane] = ds.lo; }
+  if (lane + 64 < nd) { a.mv_dst[bw + lane + 64] = dq.hi; a.mv_src[bw + lane + 64] = ds.hi; }
+  if (lane == 0) *a.n_moves = bw + nd;
+}
+
+__global__ __launch_bounds__(64) void plan_kernel(GeppArgs a) { plan_body(a); }
+
+__global__ __launch_bounds__(64) void plan_batched_kernel(const GeppArgs* list) {
+  const GeppArgs a = list[blockIdx.x];
+  plan_body(a);
+}
+
+hipError_t launch_plan(const GeppArgs& a, hipStream_t stream) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_batched(const GeppArgs* list, int count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(plan_batched_kernel, dim3(count), dim3(64), 0, stream, list);
+  return hipGetLastError();
+}
+
+// Pi11 on the top bw rows: row k0+i takes row k0+p11[i] in the columns left
+// of the panel (32-column strips per workgroup) and in perm (workgroup 0).
+__device__ __forceinline__ void perm_top_body(const PermTopArgs& a, int bx) {
+  __shared__ double buf[kMaxB][33];
+  __shared__ int64_t pbuf[kMaxB];
+  const int tid = threadIdx.x;
+  const int bw = a.bw;
+  const int cc = tid & 31, r8 = tid >> 5;      // 8 rows per pass
+  const int64_t col = (int64_t)bx * 32 + cc;
+  const bool cv = col < a.k0;
+  for (int i = r8; i < bw; i += 8)
+    buf[i][cc] = cv ? a.A[(a.k0 + a.p11[i]) * a.lda + col] : 0.0;
+  if (bx == 0 && tid < bw) pbuf[tid] = a.perm[a.k0 + a.p11[tid]];
+  __syncthreads();
+  if (cv)
+    for (int i = r8; i < bw; i += 8) a.A[(a.k0 + i) * a.lda + col] = buf[i][cc];
+  if (bx == 0 && tid < bw) a.perm[a.k0 + tid] = pbuf[tid];
+}
+
+__global__ __launch_bounds__(256) void perm_top_kernel(PermTopArgs a) { perm_top_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void perm_top_batched_kernel(const PermTopArgs* list) {
+  const PermTopArgs a = list[blockIdx.y];
+  if (blockIdx.x > 0 && (int64_t)blockIdx.x * 32 >= a.k0) return;
+  perm_top_body(a, blockIdx.x);
+}
+
+hipError_t launch_perm_top(const PermTopArgs& a, hipStream_t stream) {
+  const int64_t grid = std::max<int64_t>(1, (a.k0 + 31) / 32);
+  hipLaunchKernelGGL(perm_top_kernel, dim3((unsigned)grid), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_perm_top_batched(const PermTopArgs* list, int count, int64_t max_k0,
+                                   hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  const int64_t grid = std::max<int64_t>(1, (max_k0 + 31) / 32);
+  hipLaunchKernelGGL(perm_top_batched_kernel, dim3((unsigned)grid, (unsigned)count), dim3(256), 0,
+                     stream, list);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kGeppThreads) void gepp_kernel(GeppArgs a) { gepp_body(a); }
@@ -297,7 +352,7 @@ __global__ __launch_bounds__(kGeppThreads) void gepp_batched_kernel(const GeppAr
 }
 
 size_t gepp_smem_bytes(int bw) {
-  return sizeof(double) * (size_t)(bw * (bw + 1)) + sizeof(int) * (5 * kMaxB + 16);
+  return sizeof(double) * (size_t)(bw * (bw + 1)) + sizeof(int) * (2 * kMaxB + 8);
 }
 
 hipError_t launch_gepp(const GeppArgs& a, hipStream_t stream) {
@@ -450,7 +505,8 @@ __device__ __forceinline__ void trsm_u12_body(const TrsmArgs& t, int bx) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int r = l8 + 8 * k;
-    x[k] = (cv && r < bw) ? col[(int64_t)r * lda] : 0.0;
+    const int rs = (r < bw && t.p11) ? t.p11[r] : r;     // Pi11^T A12
+    x[k] = (cv && r < bw) ? col[(int64_t)rs * lda] : 0.0;
   }
   __syncthreads();
 #pragma unroll
@@ -502,7 +558,7 @@ __global__ __launch_bounds__(256) void trsm_u12_batched_kernel(const TrsmArgs* l
 }
 
 hipError_t launch_trsm_u12(double* A, int64_t lda, int64_t k0, int bw, int64_t nr, double* amax1,
-                           double* amax2, hipStream_t stream) {
+                           double* amax2, const int32_t* p11, hipStream_t stream) {
   if (nr <= 0) return hipSuccess;
   static bool attr_done = false;
   const size_t smem = sizeof(double) * (size_t)(kMaxB * (kMaxB - 1) / 2 + 1);
@@ -513,7 +569,7 @@ hipError_t launch_trsm_u12(double* A, int64_t lda, int64_t k0, int bw, int64_t n
     attr_done = true;
   }
   const int64_t grid = (nr + kTrsmCols - 1) / kTrsmCols;
-  TrsmArgs t{A, lda, k0, bw, nr, amax1, amax2};
+  TrsmArgs t{A, lda, k0, bw, nr, amax1, amax2, p11};
   hipLaunchKernelGGL(trsm_u12_kernel, dim3((unsigned)grid), dim3(256),
                      sizeof(double) * (size_t)(bw * (bw - 1) / 2 + 1), stream, t);
   return hipGetLastError();

@@ -75,14 +75,32 @@ struct GeppArgs {
   int m;                      // panel rows
   const int32_t* sel;         // [bw] selected panel rows in slot order
   double* PL;                 // [bw][bw]  Pi11 L11 (row p11[j] = row j of L11)
-  int32_t* mv_dst;            // [2 kMaxB] row moves: panel position <- panel row
+  int32_t* mv_dst;            // [2 kMaxB] row moves of Pi_j: panel position <- panel row
   int32_t* mv_src;
   int32_t* n_moves;
   prrp_stats* stats;
+  int32_t* p11;               // [bw] GEPP output: slot of the row at each final position
 };
+// Moves of Pi_j^T from the selection (sel, bw -> mv_dst, mv_src, n_moves).
+hipError_t launch_plan(const GeppArgs& a, hipStream_t stream);
+hipError_t launch_plan_batched(const GeppArgs* list, int count, hipStream_t stream);
+
+// Pi11 on the top bw rows of the panel at k0: columns left of the panel and perm.
+struct PermTopArgs {
+  double* A;
+  int64_t lda;
+  int64_t k0;
+  int bw;
+  int64_t* perm;
+  const int32_t* p11;
+};
+hipError_t launch_perm_top(const PermTopArgs& a, hipStream_t stream);
+hipError_t launch_perm_top_batched(const PermTopArgs* list, int count, int64_t max_k0,
+                                   hipStream_t stream);
 hipError_t launch_gepp(const GeppArgs& a, hipStream_t stream);
+// U12 = L11^-1 Pi11^T A12 in place (p11 nullable: identity).
 hipError_t launch_trsm_u12(double* A, int64_t lda, int64_t k0, int bw, int64_t nr, double* amax1,
-                           double* amax2, hipStream_t stream);
+                           double* amax2, const int32_t* p11, hipStream_t stream);
 
 struct MoveArgs {
   double* A;
@@ -108,6 +126,7 @@ struct TrsmArgs {
   int64_t nr;
   double* amax1;              // nullable: max |U12| recorded here
   double* amax2;              // nullable: and here
+  const int32_t* p11;         // nullable: rows of A12 taken in this order (Pi11^T A12)
 };
 
 // Batched forms: one problem per entry of a device-resident list; the grid
