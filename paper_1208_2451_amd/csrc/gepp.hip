@@ -243,37 +243,42 @@ __device__ __forceinline__ void gepp_body(const GeppArgs& a) {
 }
 
 // Moves of Pi_j^T (one wave; plan in registers).
+// Lane-array helpers without branches (e is wave-uniform).
+__device__ __forceinline__ int la_get(const LaneArr& A, int e) {
+  return __builtin_amdgcn_readlane(e < 64 ? A.lo : A.hi, e & 63);
+}
+__device__ __forceinline__ void la_set(LaneArr& A, bool c, int e, int v, int lane) {
+  A.lo = (c && lane == e) ? v : A.lo;
+  A.hi = (c && lane + 64 == e) ? v : A.hi;
+}
+
 __device__ __forceinline__ void plan_body(const GeppArgs& a) {
-  __shared__ int ssel[kMaxB];
   const int bw = a.bw;
   const int lane = threadIdx.x;
-  ssel[lane] = lane < bw ? a.sel[lane] : 0;
-  ssel[lane + 64] = lane + 64 < bw ? a.sel[lane + 64] : 0;
-  __syncthreads();
+  // the selection in registers (two entries per lane), read by lane
+  const LaneArr ssel{lane < bw ? a.sel[lane] : 0, lane + 64 < bw ? a.sel[lane + 64] : 0};
   LaneArr top{lane, lane + 64}, pos{lane, lane + 64}, rec{0, 0}, dq{0, 0}, ds{0, 0};
   int nd = 0;
   for (int i = 0; i < bw; ++i) {
-    const int r = __builtin_amdgcn_readfirstlane(ssel[i]);
-    const int q = (r < bw) ? pos.get(r) : r;
+    const int r = la_get(ssel, i);
+    const bool rin = r < bw;                       // the selected row starts in the top block
+    const int pr = la_get(pos, rin ? r : 0);
+    const int q = rin ? pr : r;                    // its current position
     if (q == i) continue;
-    const int d = top.get(i);
-    top.set(i, r, lane);
-    if (r < bw) pos.set(r, i, lane);
-    if (q < bw) {
-      top.set(q, d, lane);
-      pos.set(d, q, lane);
-    } else {
-      int k;
-      if (r < bw) {
-        k = rec.get(r);
-      } else {
-        k = nd++;
-        dq.set(k, q, lane);
-      }
-      ds.set(k, d, lane);
-      rec.set(d, k, lane);
-      pos.set(d, q, lane);
-    }
+    const int d = la_get(top, i);                  // the row it displaces
+    la_set(top, true, i, r, lane);
+    la_set(pos, rin, r, i, lane);
+    const bool qin = q < bw;
+    // q inside the top block: a plain transposition there
+    la_set(top, qin, q, d, lane);
+    // q outside: d leaves the block for position q, recorded as a move
+    const int kr = la_get(rec, rin ? r : 0);
+    const int k = rin ? kr : nd;
+    la_set(dq, !qin && !rin, k, q, lane);
+    la_set(ds, !qin, k, d, lane);
+    la_set(rec, !qin, d, k, lane);
+    la_set(pos, true, d, q, lane);
+    nd += (!qin && !rin) ? 1 : 0;
   }
   // top positions take the selected rows in slot order
   if (lane < bw) { a.mv_dst[lane] = lane; a.mv_src[lane] = top.lo; }
