@@ -59,6 +59,7 @@ struct Smem {
   double* scal;    // [8]   beta, gamma, ...
   uint64_t* red;   // [16]  reduction scratch
   int* selpos;     // [kMaxB] tile positions in slot order
+  double* vw;      // [waves][2 kMaxB] per-wave reflector vectors
   int* flags;      // [8]   0: abort, 1: rank deficient, 2: winner slot,
                    //       3: exchange slot, 4: failed wait of the key poll
 };
@@ -66,7 +67,8 @@ struct Smem {
 }  // namespace
 
 size_t srrqr_smem_bytes(int bw) {
-  return sizeof(double) * (size_t)(bw * (bw + 1) / 2 + 4 * kMaxB + 8) + sizeof(uint64_t) * 16 +
+  return sizeof(double) * (size_t)(bw * (bw + 1) / 2 + 4 * kMaxB + 8) +
+         sizeof(double) * (size_t)(kThreads / 64) * 2 * kMaxB + sizeof(uint64_t) * 16 +
          sizeof(int) * (kMaxB + 8);
 }
 
@@ -89,7 +91,8 @@ void srrqr_kernel(SrrqrArgs a) {
   S.prow = S.vsh + kMaxB;
   S.rdiag = S.prow + 2 * kMaxB;
   S.scal = S.rdiag + kMaxB;
-  S.red = reinterpret_cast<uint64_t*>(S.scal + 8);
+  S.vw = S.scal + 8;
+  S.red = reinterpret_cast<uint64_t*>(S.vw + (kThreads / 64) * 2 * kMaxB);
   S.selpos = reinterpret_cast<int*>(S.red + 16);
   S.flags = S.selpos + kMaxB;
 
@@ -212,14 +215,16 @@ void srrqr_kernel(SrrqrArgs a) {
         for (int i = lane; i < sp; i += 64) S.R[sp * (sp + 1) / 2 + i] = S.prow[i];
         if (lane == 0) S.R[sp * (sp + 1) / 2 + sp] = alpha;
       }
+      // the reflector, zero left of sp, through this wave's own LDS vector
+      // (written and read by the same wave: no barrier, no per-element selects)
+      double* vw = S.vw + wave * 2 * kMaxB;
+      vw[c0] = (c0 == sp) ? v0 : x0;
+      vw[c1] = x1;
+      if (lane < sp) vw[lane] = 0.0;
+      if (lane + 64 < sp) vw[lane + 64] = 0.0;
       double vr[CPT];
 #pragma unroll
-      for (int k = 0; k < CPT; ++k) vr[k] = S.prow[l8 + 8 * k];    // all loads first
-#pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        const int c = l8 + 8 * k;
-        vr[k] = (c > sp) ? vr[k] : (c == sp ? v0 : 0.0);
-      }
+      for (int k = 0; k < CPT; ++k) vr[k] = vw[l8 + 8 * k];
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         if (live[q] && !chosen[q]) {
@@ -239,13 +244,19 @@ void srrqr_kernel(SrrqrArgs a) {
     int wbad = 0;
     if (a.mode == 0) {
       uint64_t best = 0;
+      // 0/1 masks of the trailing columns c >= s, shared by the rows (columns
+      // past bw hold zeros); the high word alone encodes 1.0 or 0.0
+      double cm[CPT];
+#pragma unroll
+      for (int k = 0; k < CPT; ++k)
+        cm[k] = __hiloint2double((l8 + 8 * k >= s) ? 0x3FF00000 : 0, 0);
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         double nn[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
-          const int c = l8 + 8 * k;
-          nn[k & 3] = (c >= s && c < bw) ? fma(x[q][k], x[q][k], nn[k & 3]) : nn[k & 3];
+          const double xm = x[q][k] * cm[k];
+          nn[k & 3] = fma(xm, xm, nn[k & 3]);
         }
         const double nu = sum8((nn[0] + nn[1]) + (nn[2] + nn[3]));
         const uint64_t key = (live[q] && !chosen[q]) ? make_key(nu, (uint32_t)tpos[q]) : 0ull;
