@@ -159,8 +159,9 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
  * over all problems still active; each system ends with exactly the factors,
  * permutation and statistics prrp_factor_mixed gives it alone.  With
  * use_graph the sequence is captured into a HIP graph on the first run and
- * replayed afterwards.  Runs of one plan must not overlap; plans that run
- * concurrently share four fork streams for their refinements. */
+ * replayed afterwards.  The refinement of all systems runs as one launch per
+ * refinement sub-step over the batch, each system stopping on its own test.
+ * Runs of one plan must not overlap. */
 int prrp_batch_plan_workspace_size(int64_t count, const int64_t* n, const int* b,
                                    const int64_t* nrhs, int rows_per_wg, size_t* bytes);
 int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,

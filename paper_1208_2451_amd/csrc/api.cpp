@@ -908,7 +908,8 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
 // the step are one launch each over all active problems.  Its device memory
 // (work lists and per-problem workspaces) is a caller-provided workspace.
 // The launch sequence can be captured once into a HIP graph and replayed;
-// optional per-problem refinement runs on fork streams inside the sequence.
+// optional refinement of every system runs as one launch per sub-step over
+// the whole batch.
 // ==========================================================================
 namespace {
 
@@ -941,29 +942,6 @@ struct PlanOp {
   int srrqr_index;     // OP_SRRQR: index into srrqr_args
 };
 
-constexpr int kForks = 4;
-
-struct ForkPool {
-  int dev = -1;
-  hipStream_t s[kForks] = {};
-};
-ForkPool g_forks;
-
-hipError_t fork_streams(hipStream_t** out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (g_forks.dev != dev) {
-    for (auto& f : g_forks.s) {
-      e = hipStreamCreateWithFlags(&f, hipStreamNonBlocking);
-      if (e != hipSuccess) return e;
-    }
-    g_forks.dev = dev;
-  }
-  *out = g_forks.s;
-  return hipSuccess;
-}
-
 struct BatchPlan {
   double tau = 2.0;
   int schur = 0;
@@ -981,10 +959,8 @@ struct BatchPlan {
   std::vector<PlanOp> ops;
   std::vector<SrrqrArgs> srrqr_args;
   std::vector<size_t> srrqr_list_off;
-  int nforks = 0;
-  hipStream_t* forks = nullptr;
-  hipEvent_t ev_fork = nullptr;
-  hipEvent_t ev_join[kForks] = {};
+  size_t ir_list_off = 0;           // refinement work list (relative to lists_at)
+  int64_t max_n = 0, max_nrhs = 0;
   hipStream_t cap = nullptr;        // private stream the graph is captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1155,6 +1131,15 @@ void plan_build(BatchPlan& P) {
                              maxbw, maxnr, 0, 0, -1});
     }
   }
+  if (P.refine) {
+    std::vector<IrArgs> irl(count);
+    std::memset(irl.data(), 0, irl.size() * sizeof(IrArgs));
+    P.ir_list_off = put(irl.data(), irl.size() * sizeof(IrArgs));
+    for (auto& q : P.p) {
+      P.max_n = std::max(P.max_n, q.n);
+      P.max_nrhs = std::max(P.max_nrhs, q.nrhs);
+    }
+  }
   P.need = P.lists_at + host.size();
 }
 
@@ -1201,8 +1186,18 @@ void plan_relocate(BatchPlan& P) {
     }
     o.off += P.lists_at;
   }
-  for (auto& q : P.p)
-    if (P.refine) q.sws = base + q.off_sws;
+  if (P.refine) {
+    IrArgs* irl = reinterpret_cast<IrArgs*>(P.host.data() + P.ir_list_off);
+    int32_t* iters = reinterpret_cast<int32_t*>(base + P.off_iters);
+    double* rels = reinterpret_cast<double*>(base + P.off_rels);
+    for (size_t i = 0; i < P.p.size(); ++i) {
+      PlanProblem& q = P.p[i];
+      q.sws = base + q.off_sws;
+      SolveWs w(q.sws, q.n, q.nrhs);
+      irl[i] = IrArgs{q.A0, q.n, q.lda, q.A, q.perm, q.B, q.X, q.nrhs, w.t1, w.t2, w.r, w.mx,
+                      w.ticket, w.ir, iters + i, rels + i};
+    }
+  }
 }
 
 hipError_t plan_enqueue(BatchPlan& P, hipStream_t st) {
@@ -1240,28 +1235,9 @@ hipError_t plan_enqueue(BatchPlan& P, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   if (P.refine) {
-    int32_t* iters = reinterpret_cast<int32_t*>(P.base + P.off_iters);
-    double* rels = reinterpret_cast<double*>(P.base + P.off_rels);
-    e = hipEventRecord(P.ev_fork, st);
+    e = launch_refine_batched(reinterpret_cast<const IrArgs*>(P.base + P.lists_at + P.ir_list_off),
+                              (int)P.p.size(), P.max_n, P.max_nrhs, P.tol, P.max_iter, st);
     if (e != hipSuccess) return e;
-    for (int f = 0; f < P.nforks; ++f) {
-      e = hipStreamWaitEvent(P.forks[f], P.ev_fork, 0);
-      if (e != hipSuccess) return e;
-    }
-    for (size_t i = 0; i < P.p.size(); ++i) {
-      const PlanProblem& q = P.p[i];
-      hipStream_t fs = P.forks[i % P.nforks];
-      const int rc = prrp_refine_async(q.A0, q.A, q.n, q.lda, q.perm, q.B, q.X, q.nrhs, q.nrhs,
-                                       P.tol, P.max_iter, iters + i, rels + i, q.sws, q.sws_bytes,
-                                       fs);
-      if (rc != 0) return hipErrorInvalidValue;
-    }
-    for (int f = 0; f < P.nforks; ++f) {
-      e = hipEventRecord(P.ev_join[f], P.forks[f]);
-      if (e != hipSuccess) return e;
-      e = hipStreamWaitEvent(st, P.ev_join[f], 0);
-      if (e != hipSuccess) return e;
-    }
   }
   return hipSuccess;
 }
@@ -1270,9 +1246,6 @@ void plan_free(BatchPlan* P) {
   if (!P) return;
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   if (P->graph) (void)hipGraphDestroy(P->graph);
-  for (int f = 0; f < kForks; ++f)
-    if (P->ev_join[f]) (void)hipEventDestroy(P->ev_join[f]);
-  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->cap) (void)hipStreamDestroy(P->cap);
   delete P;
 }
@@ -1364,13 +1337,6 @@ int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, co
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = srrqr_prepare();
   if (e == hipSuccess) e = prepare_batched_kernels();
-  if (e == hipSuccess && P->refine) {
-    e = fork_streams(&P->forks);
-    P->nforks = (int)std::min<int64_t>(kForks, count);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
-    for (int f = 0; f < P->nforks && e == hipSuccess; ++f)
-      e = hipEventCreateWithFlags(&P->ev_join[f], hipEventDisableTiming);
-  }
   if (e != hipSuccess) { plan_free(P); return herr(e); }
   P->base = static_cast<char*>(workspace);
   plan_relocate(*P);

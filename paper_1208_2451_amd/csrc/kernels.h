@@ -191,6 +191,27 @@ hipError_t launch_ir_init(IrState* st, double* mx, int64_t nrhs, int32_t* iters_
                           double* rel_out, hipStream_t s);
 hipError_t launch_ir_check(IrState* st, double* mx, int64_t nrhs, double tol, int max_iter,
                            int32_t* iters_out, double* rel_out, hipStream_t s);
+
+// One system of a batched refinement (right-hand sides with ld = nrhs; the
+// buffers are the system's solve workspace).
+struct IrArgs {
+  const double* A;            // original matrix
+  int64_t n, lda;
+  const double* LU;           // factors (lda)
+  const int64_t* perm;
+  const double* B;
+  double* X;
+  int64_t nrhs;
+  double *t1, *t2, *r, *mx;
+  uint32_t* ticket;           // [2]
+  IrState* st;
+  int32_t* iters_out;
+  double* rel_out;
+};
+// The whole refinement loop of prrp_refine_async for every system of a list,
+// one launch per sub-step over all systems.
+hipError_t launch_refine_batched(const IrArgs* list, int count, int64_t max_n, int64_t max_nrhs,
+                                 double tol, int max_iter, hipStream_t s);
 hipError_t launch_build_lists(const int32_t* child_sel, int nchild, int bw, int32_t* lists,
                               int32_t* promoted_out, int npairs, int flat_tile_start,
                               int flat_tile_len, hipStream_t s);

@@ -12,6 +12,8 @@
 // residual_kernel: r = b - A x with the error-free transformations TwoProduct
 // (by FMA) and TwoSum, accumulated per lane as in Ogita, Rump and Oishi's Dot2
 // and combined across the wave by error-free pairwise sums, rounded once.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -24,18 +26,25 @@ constexpr int RC = 8;    // right-hand sides per pass
 
 // X = B[perm] (row gather); also resets the solve's tickets and fills the
 // first solve's output Y with the sentinel.
-__global__ void gather_rows_kernel(const double* B, int64_t ldb, const int64_t* perm, double* X,
-                                   int64_t ldx, int64_t n, int64_t nrhs, double* Y, int64_t ldy,
-                                   uint32_t* tickets, const uint32_t* skip) {
+__device__ __forceinline__ void gather_rows_body(const double* B, int64_t ldb, const int64_t* perm,
+                                                 double* X, int64_t ldx, int64_t n, int64_t nrhs,
+                                                 double* Y, int64_t ldy, uint32_t* tickets,
+                                                 const uint32_t* skip, int bx, int nbx) {
   if (skip && *skip) return;
   const int64_t total = n * nrhs;
-  if (blockIdx.x == 0 && threadIdx.x < 2 && tickets) tickets[threadIdx.x] = 0u;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  if (bx == 0 && threadIdx.x < 2 && tickets) tickets[threadIdx.x] = 0u;
+  for (int64_t e = bx * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)nbx * blockDim.x) {
     const int64_t i = e / nrhs, r = e - i * nrhs;
     X[i * ldx + r] = B[perm[i] * ldb + r];
     if (Y) reinterpret_cast<uint64_t*>(Y)[i * ldy + r] = kKeySent;
   }
+}
+
+__global__ void gather_rows_kernel(const double* B, int64_t ldb, const int64_t* perm, double* X,
+                                   int64_t ldx, int64_t n, int64_t nrhs, double* Y, int64_t ldy,
+                                   uint32_t* tickets, const uint32_t* skip) {
+  gather_rows_body(B, ldb, perm, X, ldx, n, nrhs, Y, ldy, tickets, skip, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm, double* X,
@@ -49,11 +58,10 @@ hipError_t launch_gather_rows(const double* B, int64_t ldb, const int64_t* perm,
 }
 
 template <bool LOWER, int RCT>
-__global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, int64_t lda,
-                                                   const double* Bin, int64_t ldb, double* Yout,
-                                                   int64_t ld, int64_t nrhs, uint32_t* ticket,
-                                                   double* Fill, int64_t ldf,
-                                                   const uint32_t* skip) {
+__device__ __forceinline__ void trsv_body(const double* LU, int64_t n, int64_t lda,
+                                          const double* Bin, int64_t ldb, double* Yout, int64_t ld,
+                                          int64_t nrhs, uint32_t* ticket, double* Fill, int64_t ldf,
+                                          const uint32_t* skip) {
   if (skip && *skip) return;
   // Yout starts out holding the sentinel; every solution value is written
   // exactly once, so dependent blocks poll the values they need.
@@ -182,6 +190,15 @@ __global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, 
   }
 }
 
+template <bool LOWER, int RCT>
+__global__ __launch_bounds__(256) void trsv_kernel(const double* LU, int64_t n, int64_t lda,
+                                                   const double* Bin, int64_t ldb, double* Yout,
+                                                   int64_t ld, int64_t nrhs, uint32_t* ticket,
+                                                   double* Fill, int64_t ldf,
+                                                   const uint32_t* skip) {
+  trsv_body<LOWER, RCT>(LU, n, lda, Bin, ldb, Yout, ld, nrhs, ticket, Fill, ldf, skip);
+}
+
 hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, const double* Bin,
                                int64_t ldb, double* Yout, int64_t ld, int64_t nrhs, int lower,
                                uint32_t* ticket, double* Fill, int64_t ldf, const uint32_t* skip,
@@ -208,13 +225,13 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
   e = (a - (s - bb)) + (b - bb);
 }
 
-__global__ __launch_bounds__(256) void residual_kernel(const double* A, int64_t n, int64_t lda,
-                                                       const double* X, int64_t ldx, const double* B,
-                                                       int64_t ldb, double* R, int64_t ldr,
-                                                       int64_t nrhs, const uint32_t* skip) {
+__device__ __forceinline__ void residual_body(const double* A, int64_t n, int64_t lda,
+                                              const double* X, int64_t ldx, const double* B,
+                                              int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
+                                              const uint32_t* skip, int bx) {
   if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t row = (int64_t)bx * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const double* arow = A + row * lda;
   for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RC) {
@@ -258,6 +275,13 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* A, int64_t 
   }
 }
 
+__global__ __launch_bounds__(256) void residual_kernel(const double* A, int64_t n, int64_t lda,
+                                                       const double* X, int64_t ldx, const double* B,
+                                                       int64_t ldb, double* R, int64_t ldr,
+                                                       int64_t nrhs, const uint32_t* skip) {
+  residual_body(A, n, lda, X, ldx, B, ldb, R, ldr, nrhs, skip, blockIdx.x);
+}
+
 hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double* X, int64_t ldx,
                            const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
                            const uint32_t* skip, hipStream_t s) {
@@ -269,11 +293,11 @@ hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double
 
 // X += D; out[2r] = max|D(:,r)|, out[2r+1] = max|X(:,r)| (out zeroed by the caller).
 // One thread per row; maxima reduced per wave before the device-scope max.
-__global__ __launch_bounds__(256) void axpy_maxrel_kernel(double* X, int64_t ldx, const double* D,
-                                                          int64_t ldd, int64_t n, int64_t nrhs,
-                                                          double* out, const uint32_t* skip) {
+__device__ __forceinline__ void axpy_maxrel_body(double* X, int64_t ldx, const double* D,
+                                                 int64_t ldd, int64_t n, int64_t nrhs, double* out,
+                                                 const uint32_t* skip, int bx) {
   if (skip && *skip) return;
-  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  const int64_t i = bx * (int64_t)256 + threadIdx.x;
   for (int64_t r = 0; r < nrhs; ++r) {
     double dm = 0.0, xm = 0.0;
     if (i < n) {
@@ -295,6 +319,12 @@ __global__ __launch_bounds__(256) void axpy_maxrel_kernel(double* X, int64_t ldx
   }
 }
 
+__global__ __launch_bounds__(256) void axpy_maxrel_kernel(double* X, int64_t ldx, const double* D,
+                                                          int64_t ldd, int64_t n, int64_t nrhs,
+                                                          double* out, const uint32_t* skip) {
+  axpy_maxrel_body(X, ldx, D, ldd, n, nrhs, out, skip, blockIdx.x);
+}
+
 hipError_t launch_axpy_maxrel(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t n,
                               int64_t nrhs, double* out, const uint32_t* skip, hipStream_t s) {
   const int64_t blocks = (n + 255) / 256;
@@ -308,8 +338,8 @@ hipError_t launch_axpy_maxrel(double* X, int64_t ldx, const double* D, int64_t l
 // enqueued (or captured in a graph) without host round trips: the stopping
 // test runs in ir_check_kernel and later iterations' kernels see `done` and
 // return at once.
-__global__ void ir_init_kernel(IrState* st, double* mx, int64_t nrhs, int32_t* iters_out,
-                               double* rel_out) {
+__device__ __forceinline__ void ir_init_body(IrState* st, double* mx, int64_t nrhs,
+                                             int32_t* iters_out, double* rel_out) {
   const int t = threadIdx.x;
   if (t == 0) {
     st->done = 0u;
@@ -324,8 +354,8 @@ __global__ void ir_init_kernel(IrState* st, double* mx, int64_t nrhs, int32_t* i
 // Same stopping test as the host-driven loop: stop when the correction is at
 // most tol times the solution (per right-hand side, worst case), or when it
 // no longer halves, or after max_iter corrections.
-__global__ void ir_check_kernel(IrState* st, double* mx, int64_t nrhs, double tol, int max_iter,
-                                int32_t* iters_out, double* rel_out) {
+__device__ __forceinline__ void ir_check_body(IrState* st, double* mx, int64_t nrhs, double tol,
+                                              int max_iter, int32_t* iters_out, double* rel_out) {
   if (threadIdx.x != 0 || st->done) return;
   double rel = 0.0;
   for (int64_t r = 0; r < nrhs; ++r) {
@@ -342,6 +372,15 @@ __global__ void ir_check_kernel(IrState* st, double* mx, int64_t nrhs, double to
   if (rel_out) *rel_out = rel;
 }
 
+__global__ void ir_init_kernel(IrState* st, double* mx, int64_t nrhs, int32_t* iters_out,
+                               double* rel_out) {
+  ir_init_body(st, mx, nrhs, iters_out, rel_out);
+}
+__global__ void ir_check_kernel(IrState* st, double* mx, int64_t nrhs, double tol, int max_iter,
+                                int32_t* iters_out, double* rel_out) {
+  ir_check_body(st, mx, nrhs, tol, max_iter, iters_out, rel_out);
+}
+
 hipError_t launch_ir_init(IrState* st, double* mx, int64_t nrhs, int32_t* iters_out,
                           double* rel_out, hipStream_t s) {
   hipLaunchKernelGGL(ir_init_kernel, dim3(1), dim3(64), 0, s, st, mx, nrhs, iters_out, rel_out);
@@ -352,6 +391,76 @@ hipError_t launch_ir_check(IrState* st, double* mx, int64_t nrhs, double tol, in
                            int32_t* iters_out, double* rel_out, hipStream_t s) {
   hipLaunchKernelGGL(ir_check_kernel, dim3(1), dim3(64), 0, s, st, mx, nrhs, tol, max_iter,
                      iters_out, rel_out);
+  return hipGetLastError();
+}
+
+
+// ----------------------------------------- refinement of a batch of systems
+// One launch per refinement sub-step over all systems of a batch (system
+// blockIdx.y of the list); surplus workgroups of smaller systems exit, and a
+// system that has met its stopping test skips its remaining work.  phase 0:
+// the first solve of B into X; phase 1: the correction solve of R in place.
+__global__ void ir_init_batched_kernel(const IrArgs* list) {
+  const IrArgs a = list[blockIdx.x];
+  ir_init_body(a.st, a.mx, a.nrhs, a.iters_out, a.rel_out);
+}
+
+__global__ void gather_batched_kernel(const IrArgs* list, int phase) {
+  const IrArgs a = list[blockIdx.y];
+  const int64_t nb = (a.n * a.nrhs + 255) / 256;
+  if ((int64_t)blockIdx.x >= nb) return;
+  gather_rows_body(phase ? a.r : a.B, a.nrhs, a.perm, a.t1, a.nrhs, a.n, a.nrhs, a.t2, a.nrhs,
+                   a.ticket, phase ? &a.st->done : nullptr, blockIdx.x, (int)nb);
+}
+
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trsv_batched_kernel(const IrArgs* list, int phase) {
+  const IrArgs a = list[blockIdx.y];
+  double* out = phase ? a.r : a.X;
+  if (LOWER)
+    trsv_body<true, RC>(a.LU, a.n, a.lda, a.t1, a.nrhs, a.t2, a.nrhs, a.nrhs, a.ticket, out,
+                        a.nrhs, phase ? &a.st->done : nullptr);
+  else
+    trsv_body<false, RC>(a.LU, a.n, a.lda, a.t2, a.nrhs, out, a.nrhs, a.nrhs, a.ticket + 1,
+                         nullptr, 0, phase ? &a.st->done : nullptr);
+}
+
+__global__ __launch_bounds__(256) void residual_batched_kernel(const IrArgs* list) {
+  const IrArgs a = list[blockIdx.y];
+  residual_body(a.A, a.n, a.lda, a.X, a.nrhs, a.B, a.nrhs, a.r, a.nrhs, a.nrhs, &a.st->done,
+                blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void axpy_batched_kernel(const IrArgs* list) {
+  const IrArgs a = list[blockIdx.y];
+  axpy_maxrel_body(a.X, a.nrhs, a.r, a.nrhs, a.n, a.nrhs, a.mx, &a.st->done, blockIdx.x);
+}
+
+__global__ void ir_check_batched_kernel(const IrArgs* list, double tol, int max_iter) {
+  const IrArgs a = list[blockIdx.x];
+  ir_check_body(a.st, a.mx, a.nrhs, tol, max_iter, a.iters_out, a.rel_out);
+}
+
+hipError_t launch_refine_batched(const IrArgs* list, int count, int64_t max_n, int64_t max_nrhs,
+                                 double tol, int max_iter, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const unsigned gb = (unsigned)std::max<int64_t>(1, (max_n * max_nrhs + 255) / 256);
+  const unsigned tb = (unsigned)((max_n + NB - 1) / NB);
+  const unsigned rb = (unsigned)((max_n + 3) / 4);
+  const unsigned ab = (unsigned)((max_n + 255) / 256);
+  const unsigned c = (unsigned)count;
+  hipLaunchKernelGGL(ir_init_batched_kernel, dim3(c), dim3(64), 0, s, list);
+  hipLaunchKernelGGL(gather_batched_kernel, dim3(gb, c), dim3(256), 0, s, list, 0);
+  hipLaunchKernelGGL((trsv_batched_kernel<true>), dim3(tb, c), dim3(256), 0, s, list, 0);
+  hipLaunchKernelGGL((trsv_batched_kernel<false>), dim3(tb, c), dim3(256), 0, s, list, 0);
+  for (int it = 1; it <= max_iter; ++it) {
+    hipLaunchKernelGGL(residual_batched_kernel, dim3(rb, c), dim3(256), 0, s, list);
+    hipLaunchKernelGGL(gather_batched_kernel, dim3(gb, c), dim3(256), 0, s, list, 1);
+    hipLaunchKernelGGL((trsv_batched_kernel<true>), dim3(tb, c), dim3(256), 0, s, list, 1);
+    hipLaunchKernelGGL((trsv_batched_kernel<false>), dim3(tb, c), dim3(256), 0, s, list, 1);
+    hipLaunchKernelGGL(axpy_batched_kernel, dim3(ab, c), dim3(256), 0, s, list);
+    hipLaunchKernelGGL(ir_check_batched_kernel, dim3(c), dim3(64), 0, s, list, tol, max_iter);
+  }
   return hipGetLastError();
 }
 
