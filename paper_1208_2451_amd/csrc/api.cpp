@@ -73,12 +73,13 @@ Tiles tile_bounds(int64_t m, int64_t tile_rows, int b) {
 // whose latency grows with the number of workgroups polled (~1.8 us at 64,
 // ~3.3 us at 256 on MI355X), while fewer workgroups mean more rows each (at
 // most 128, the register budget).  Default: at most 64 rows per workgroup,
-// at most PRRP_PANEL_WGS (default 128) workgroups; none left without rows.
+// at most PRRP_PANEL_WGS (default 64, the CUs the look-ahead keeps free of
+// the trailing update) workgroups; none left without rows.
 int panel_wg_cap() {
   static int cap = 0;
   if (cap == 0) {
     const char* e = getenv("PRRP_PANEL_WGS");
-    cap = e ? atoi(e) : 128;
+    cap = e ? atoi(e) : 64;
     if (cap < 1) cap = 1;
     if (cap > 256) cap = 256;
   }
