@@ -135,7 +135,7 @@ Layout make_layout(int64_t n, int b, int method, int64_t tile_rows) {
   L.sel_stride = (size_t)groups * kMaxB;
   L.off_pl = off;     off += align_up((size_t)b * b * 8, 256);
   L.off_p11 = off;    off += align_up((size_t)kMaxB * 4, 256);
-  L.off_moves = off;  off += align_up((size_t)(4 * kMaxB + 4) * 4, 256);
+  L.off_moves = off;  off += 2 * align_up((size_t)(4 * kMaxB + 4) * 4, 256);
   L.total = off;
   return L;
 }
@@ -276,7 +276,7 @@ struct Ctx {
   hipStream_t side = nullptr;        // look-ahead stream (null: no look-ahead)
   hipStream_t side2 = nullptr;       // GEPP / L21 / U12 stream (null: no look-ahead)
   hipEvent_t far_event = nullptr;    // pending far Schur update on `side`
-  hipEvent_t l21_event = nullptr;    // pending L21 of the previous panel on `side2`
+  hipEvent_t l21_hist[2] = {};       // GEPP path of the last two panels (by parity)
   int pidx = 0;                      // panel index (parity of sel / Y)
 
   uint64_t* slot_set(int parity) {
@@ -296,7 +296,12 @@ struct Ctx {
   double* Y() { return reinterpret_cast<double*>(ws + L.off_y + (size_t)(pidx & 1) * L.y_stride); }
   double* PL() { return reinterpret_cast<double*>(ws + L.off_pl); }
   int32_t* p11() { return reinterpret_cast<int32_t*>(ws + L.off_p11); }
-  int32_t* mv() { return reinterpret_cast<int32_t*>(ws + L.off_moves); }
+  // the move lists alternate too: the far and left moves of a panel run on
+  // the side streams while the next panel's plan writes the other list
+  int32_t* mv() {
+    return reinterpret_cast<int32_t*>(ws + L.off_moves +
+                                      (size_t)(pidx & 1) * align_up((size_t)(4 * kMaxB + 4) * 4, 256));
+  }
 
   // One srrqr launch; fills in the slot-set bookkeeping.
   hipError_t srrqr(SrrqrArgs& a) {
@@ -328,6 +333,17 @@ struct Ctx {
     return e;
   }
 
+  // Before a panel's strong RRQR: the GEPP path of the panel two steps back
+  // (same sel / Y buffers) must have finished reading them.
+  hipError_t before_panel() {
+    if (l21_hist[pidx & 1] != nullptr) {
+      hipError_t e = hipStreamWaitEvent(st, l21_hist[pidx & 1], 0);
+      l21_hist[pidx & 1] = nullptr;
+      return e;
+    }
+    return hipSuccess;
+  }
+
   // Steps after the pivot rows of the panel at k0 are known (sel(), Y()).
   //
   // Critical path (stream st): the moves of Pi_j, then the trailing update in
@@ -350,26 +366,28 @@ struct Ctx {
       e = launch_plan(ga, st);
     }
     if (e != hipSuccess) return e;
-    // rows may move once the previous far update and L21 have landed
+    // the previous far update writes columns moved here
     if (far_event != nullptr) {
       e = hipStreamWaitEvent(st, far_event, 0);
       if (e != hipSuccess) return e;
       far_event = nullptr;
     }
-    if (l21_event != nullptr) {
-      e = hipStreamWaitEvent(st, l21_event, 0);
-      if (e != hipSuccess) return e;
-      l21_event = nullptr;
-    }
-    MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, (m > bw) ? Yp : nullptr, b};
+    const bool la = side2 != nullptr;
+    const int64_t nr0 = n - k0 - bw;
+    const int64_t n_near0 = (side != nullptr) ? std::min<int64_t>(b, nr0) : nr0;
+    // Critical path: the rows of M^T and the next panel's columns (with
+    // look-ahead), or every column outside the panel and perm (without).
+    MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, la ? nullptr : perm,
+                (m > bw) ? Yp : nullptr, b,
+                la ? k0 + bw : 0, la ? k0 + bw + n_near0 : n, la ? n : k0, la ? 0 : bw};
     {
       PhaseScope ps(2, st);
       e = launch_moves(ma, st);
     }
     if (e != hipSuccess) return e;
-    hipStream_t gs = (side2 != nullptr) ? side2 : st;
+    hipStream_t gs = la ? side2 : st;
     hipEvent_t ev_moved = nullptr, ev_near = nullptr, ev_far = nullptr;
-    if (side2 != nullptr) {
+    if (la) {
       ev_moved = side_event();
       e = hipEventRecord(ev_moved, st);
       if (e != hipSuccess) return e;
@@ -397,6 +415,14 @@ struct Ctx {
       if (side != nullptr && nr > n_near) {
         e = hipStreamWaitEvent(side, ev_moved, 0);
         if (e != hipSuccess) return e;
+        // the far columns move on this stream, right before their update
+        MoveArgs mf{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, nullptr, nullptr, b,
+                    k0 + bw + n_near, n, n, 0};
+        {
+          PhaseScope ps(2, side);
+          e = launch_moves(mf, side);
+        }
+        if (e != hipSuccess) return e;
         GemmArgs sc_far{(int)(m - bw), (int)(nr - n_near), bw, yrest, b, a12 + n_near, lda,
                         a22 + n_near, lda, -1.0, 1.0, &stats->max_abs_W, nullptr, schur};
         {
@@ -411,9 +437,18 @@ struct Ctx {
       }
     }
     // ---- GEPP path
-    if (side2 != nullptr) {
+    if (la) {
       e = hipStreamWaitEvent(gs, ev_moved, 0);
       if (e != hipSuccess) return e;
+      // the columns left of the panel and perm move on this stream
+      if (k0 > 0 || perm != nullptr) {
+        MoveArgs ml{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, nullptr, b, 0, k0, n, 0};
+        {
+          PhaseScope ps(2, gs);
+          e = launch_moves(ml, gs);
+        }
+        if (e != hipSuccess) return e;
+      }
     }
     {
       PhaseScope ps(1, gs);
@@ -436,8 +471,9 @@ struct Ctx {
       }
       if (e != hipSuccess) return e;
       if (side2 != nullptr) {
-        l21_event = side_event();
-        e = hipEventRecord(l21_event, gs);
+        // the strong RRQR two panels on reuses this panel's sel and Y
+        l21_hist[pidx & 1] = side_event();
+        e = hipEventRecord(l21_hist[pidx & 1], gs);
         if (e != hipSuccess) return e;
         e = hipStreamWaitEvent(gs, ev_near, 0);
         if (e != hipSuccess) return e;
@@ -526,6 +562,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
   for (int64_t k0 = 0; k0 < n; k0 += b) {
     const int bw = (int)std::min<int64_t>(b, n - k0);
     const int64_t m = n - k0;
+    PRRP_TRY(c.before_panel());
     Tiles t;
     if (method == 1) t = tile_bounds(m, tile_rows, bw);
     if (method == 0 || t.start.size() == 1) {
@@ -1094,7 +1131,7 @@ void plan_build(BatchPlan& P) {
       gl.push_back(GeppArgs{q.A, q.lda, k0, bw, (int)m, reinterpret_cast<int32_t*>(W(q.off_sel)),
                             PLp, mv_dst, mv_src, n_moves, q.stats, p11});
       ml.push_back(MoveArgs{q.A, q.lda, q.n, k0, bw, mv_dst, mv_src, n_moves, q.perm,
-                            (m > bw) ? Yp : nullptr, q.b});
+                            (m > bw) ? Yp : nullptr, q.b, 0, q.n, k0, bw});
       pl.push_back(PermTopArgs{q.A, q.lda, k0, bw, q.perm, p11});
       maxout = std::max<int64_t>(maxout, q.n - bw);
       if (m > bw) {

@@ -7,8 +7,8 @@
 // plan_kernel (one wave): Pi_j^T as the transpositions "row k0+i <-> current
 //   position of the i-th selected row" (i = 0..bw-1), reduced to a list of
 //   whole-row moves (destination position <- source row).
-// moves_kernel: applies the moves to the columns outside the panel, to perm,
-//   and to the rows of M^T that belong to displaced rows.
+// moves_kernel: applies the moves to a range of columns (outside the panel),
+//   optionally to perm, and to the rows of M^T that belong to displaced rows.
 // gepp_kernel (one workgroup): gathers the selected rows' panel block (in
 //   slot order, from their positions before the moves) and factors it with
 //   the tie rule, blocked by 8 columns: one wave factors each 8-column
@@ -403,13 +403,13 @@ __device__ __forceinline__ void moves_body(const MoveArgs& a, int bx, int nbx) {
   __shared__ int64_t pbuf[2 * kMaxB];
   const int nm = *a.n_moves;
   const int tid = threadIdx.x;
-  const int64_t outside = a.n - a.bw;          // columns outside the panel
+  const int64_t span = (a.c_end - a.c_begin) - a.skip_w;   // columns to move
   const int64_t c0 = (int64_t)bx * kStrip;
   const int cc = tid & (kStrip - 1);
   const int r8 = tid / kStrip;                 // 8 rows per pass
-  int64_t col = c0 + cc;
-  const bool cvalid = col < outside;
-  if (col >= a.k0) col += a.bw;
+  const bool cvalid = c0 + cc < span;
+  int64_t col = a.c_begin + c0 + cc;
+  if (col >= a.skip_lo) col += a.skip_w;
   for (int t0 = r8; t0 < nm; t0 += 8 * (kMoveThreads / kStrip)) {
     double v[8];
 #pragma unroll
@@ -423,13 +423,13 @@ __device__ __forceinline__ void moves_body(const MoveArgs& a, int bx, int nbx) {
       if (t < nm) buf[t][cc] = v[u];
     }
   }
-  if (bx == 0) {
+  if (bx == 0 && a.perm) {
     for (int t = tid; t < nm; t += kMoveThreads) pbuf[t] = a.perm[a.k0 + a.mv_src[t]];
   }
   __syncthreads();
   for (int t = r8; t < nm; t += kMoveThreads / kStrip)
     if (cvalid && a.mv_dst[t] != a.mv_src[t]) a.A[(a.k0 + a.mv_dst[t]) * a.lda + col] = buf[t][cc];
-  if (bx == 0) {
+  if (bx == 0 && a.perm) {
     for (int t = tid; t < nm; t += kMoveThreads) a.perm[a.k0 + a.mv_dst[t]] = pbuf[t];
   }
   // Y rows: displaced rows (moves past the top block) carry their M columns;
@@ -608,8 +608,8 @@ hipError_t launch_trsm_u12_batched(const TrsmArgs* list, int count, int bw, int6
 }
 
 hipError_t launch_moves(const MoveArgs& a, hipStream_t stream) {
-  const int64_t outside = a.n - a.bw;
-  const int64_t grid = std::max<int64_t>(1, (outside + kStrip - 1) / kStrip);
+  const int64_t span = (a.c_end - a.c_begin) - a.skip_w;
+  const int64_t grid = std::max<int64_t>(1, (span + kStrip - 1) / kStrip);
   hipLaunchKernelGGL(moves_kernel, dim3((unsigned)grid), dim3(kMoveThreads), 0, stream, a);
   return hipGetLastError();
 }

@@ -111,9 +111,12 @@ struct MoveArgs {
   const int32_t* mv_dst;
   const int32_t* mv_src;
   const int32_t* n_moves;
-  int64_t* perm;
+  int64_t* perm;              // nullable: perm entries move too
   double* Y;                  // rows of Y follow displaced rows (nullable)
   int64_t ldy;
+  int64_t c_begin, c_end;     // columns moved: [c_begin, c_end) except the
+  int64_t skip_lo;            //   skip_w columns from skip_lo
+  int skip_w;
 };
 hipError_t launch_moves(const MoveArgs& a, hipStream_t stream);
 
