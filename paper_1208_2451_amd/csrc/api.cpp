@@ -101,6 +101,7 @@ struct Layout {
   size_t slots_set_words = 0;     // words per slot set
   size_t off_slots = 0, off_rounds = 0, off_abort = 0, off_sel = 0, off_lists = 0;
   size_t off_y = 0, off_pl = 0, off_p11 = 0, off_moves = 0, off_lsel = 0;
+  size_t off_panel = 0, off_srcmap = 0, panel_stride = 0;
   size_t y_stride = 0, sel_stride = 0;   // the two panels' Y and sel buffers
   size_t total = 0;
   int max_members = 0;            // sum over groups of workgroups in any launch
@@ -136,6 +137,10 @@ Layout make_layout(int64_t n, int b, int method, int64_t tile_rows) {
   L.off_pl = off;     off += align_up((size_t)b * b * 8, 256);
   L.off_p11 = off;    off += align_up((size_t)kMaxB * 4, 256);
   L.off_moves = off;  off += 2 * align_up((size_t)(4 * kMaxB + 4) * 4, 256);
+  // the next panel's columns after the near update (two panels, n x b each)
+  L.panel_stride = align_up((size_t)n * b * 8, 256);
+  L.off_panel = off;  off += 2 * L.panel_stride;
+  L.off_srcmap = off; off += align_up((size_t)n * 4, 256);
   L.total = off;
   return L;
 }
@@ -278,6 +283,8 @@ struct Ctx {
   hipEvent_t far_event = nullptr;    // pending far Schur update on `side`
   hipEvent_t l21_hist[2] = {};       // GEPP path of the last two panels (by parity)
   int pidx = 0;                      // panel index (parity of sel / Y)
+  hipEvent_t gepp_event = nullptr;   // GEPP of the previous panel (reads its panel buffer)
+  const double* panel_src = nullptr; // this panel's columns (null: in A)
 
   uint64_t* slot_set(int parity) {
     return reinterpret_cast<uint64_t*>(ws + L.off_slots) + (size_t)parity * L.slots_set_words;
@@ -298,6 +305,10 @@ struct Ctx {
   int32_t* p11() { return reinterpret_cast<int32_t*>(ws + L.off_p11); }
   // the move lists alternate too: the far and left moves of a panel run on
   // the side streams while the next panel's plan writes the other list
+  double* panel_buf(int parity) {
+    return reinterpret_cast<double*>(ws + L.off_panel + (size_t)parity * L.panel_stride);
+  }
+  int32_t* srcmap() { return reinterpret_cast<int32_t*>(ws + L.off_srcmap); }
   int32_t* mv() {
     return reinterpret_cast<int32_t*>(ws + L.off_moves +
                                       (size_t)(pidx & 1) * align_up((size_t)(4 * kMaxB + 4) * 4, 256));
@@ -346,103 +357,117 @@ struct Ctx {
 
   // Steps after the pivot rows of the panel at k0 are known (sel(), Y()).
   //
-  // Critical path (stream st): the moves of Pi_j, then the trailing update in
-  // the block form of Algorithm "LU_PRRP factorization", A22 -= L_2j A12 with
-  // L_2j = M^T (Y) and A12 before the diagonal GEPP, which is all the next
-  // panel needs.  Off the critical path (side2): GEPP of the diagonal block,
-  // Pi11 on the left columns and perm, the stored L21 = M^T Pi11 L11 and
-  // U12 = L11^-1 Pi11^T A12 (after both parts of the trailing update have
-  // read A12).  The far part of the update runs on `side`.
+  // The trailing update is the block form of Algorithm "LU_PRRP
+  // factorization", A22 -= L_2j A12 with L_2j = M^T (Y) and A12 before the
+  // diagonal GEPP.
+  //
+  // With look-ahead the strong RRQR has already formed the moves of Pi_j and
+  // written M^T in the order after them.  Critical path (stream st): the
+  // update of the next panel's columns, gathered from their rows before the
+  // moves and written to a panel buffer, which is all the next panel reads.
+  // `side`: the far columns' moves and update.  `side2`: the moves of the
+  // columns left of the panel and of perm, GEPP of the diagonal block, Pi11 on
+  // the left columns and perm, the stored L21 = M^T Pi11 L11, the moves of the
+  // top rows in the next panel's columns, and U12 = L11^-1 Pi11^T A12.
+  // Without look-ahead all of it runs in order on st, moves first.
   hipError_t finish_panel(int64_t k0, int bw) {
     const int64_t m = n - k0;
     int32_t* mv_dst = mv();
     int32_t* mv_src = mv() + 2 * kMaxB;
     int32_t* n_moves = mv() + 4 * kMaxB;
     double* Yp = Y();
-    GeppArgs ga{A, lda, k0, bw, (int)m, sel(), PL(), mv_dst, mv_src, n_moves, stats, p11()};
-    hipError_t e;
-    {
-      PhaseScope ps(2, st);
-      e = launch_plan(ga, st);
-    }
-    if (e != hipSuccess) return e;
-    // the previous far update writes columns moved here
-    if (far_event != nullptr) {
-      e = hipStreamWaitEvent(st, far_event, 0);
-      if (e != hipSuccess) return e;
-      far_event = nullptr;
-    }
     const bool la = side2 != nullptr;
-    const int64_t nr0 = n - k0 - bw;
-    const int64_t n_near0 = (side != nullptr) ? std::min<int64_t>(b, nr0) : nr0;
-    // Critical path: the rows of M^T and the next panel's columns (with
-    // look-ahead), or every column outside the panel and perm (without).
-    MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, la ? nullptr : perm,
-                (m > bw) ? Yp : nullptr, b,
-                la ? k0 + bw : 0, la ? k0 + bw + n_near0 : n, la ? n : k0, la ? 0 : bw};
-    {
-      PhaseScope ps(2, st);
-      e = launch_moves(ma, st);
-    }
-    if (e != hipSuccess) return e;
-    hipStream_t gs = la ? side2 : st;
-    hipEvent_t ev_moved = nullptr, ev_near = nullptr, ev_far = nullptr;
-    if (la) {
-      ev_moved = side_event();
-      e = hipEventRecord(ev_moved, st);
-      if (e != hipSuccess) return e;
-    }
+    GeppArgs ga{A, lda, k0, bw, (int)m, sel(), PL(), mv_dst, mv_src, n_moves, stats, p11(),
+                panel_src, b};
+    hipError_t e;
     const int64_t nr = n - k0 - bw;
     double* a12 = A + k0 * lda + k0 + bw;
-    if (m > bw) {
-      // trailing update A22 -= M^T A12 (block form): the next panel's columns
-      // here, the rest on the side stream (look-ahead) or here
-      const double* yrest = Yp + (size_t)bw * b;
-      double* a22 = A + (k0 + bw) * lda + k0 + bw;
-      const int64_t n_near = (side != nullptr) ? std::min<int64_t>(b, nr) : nr;
-      GemmArgs sc{(int)(m - bw), (int)n_near, bw, yrest, b, a12, lda, a22, lda, -1.0, 1.0,
-                  &stats->max_abs_W, nullptr, schur};
+    double* a22 = A + (k0 + bw) * lda + k0 + bw;
+    const double* yrest = Yp + (size_t)bw * b;
+    hipStream_t gs = la ? side2 : st;
+    hipEvent_t ev_sel = nullptr, ev_near = nullptr, ev_far = nullptr;
+    int64_t n_near = nr;
+    double* next_panel = nullptr;
+    if (!la) {
       {
-        PhaseScope ps(5, st);
-        e = launch_gemm(sc, st);
+        PhaseScope ps(2, st);
+        e = launch_plan(ga, st);
       }
       if (e != hipSuccess) return e;
-      if (side2 != nullptr) {
+      MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, (m > bw) ? Yp : nullptr, b,
+                  0, n, k0, bw, 0};
+      {
+        PhaseScope ps(2, st);
+        e = launch_moves(ma, st);
+      }
+      if (e != hipSuccess) return e;
+      if (m > bw) {
+        GemmArgs sc{(int)(m - bw), (int)nr, bw, yrest, b, a12, lda, a22, lda, -1.0, 1.0,
+                    &stats->max_abs_W, nullptr, schur};
+        {
+          PhaseScope ps(5, st);
+          e = launch_gemm(sc, st);
+        }
+        if (e != hipSuccess) return e;
+      }
+    } else {
+      ev_sel = side_event();
+      e = hipEventRecord(ev_sel, st);
+      if (e != hipSuccess) return e;
+      if (m > bw) {
+        n_near = std::min<int64_t>(b, nr);
+        // the previous far update wrote these columns; the previous panel's
+        // GEPP read the buffer written here
+        if (far_event != nullptr) {
+          e = hipStreamWaitEvent(st, far_event, 0);
+          if (e != hipSuccess) return e;
+          far_event = nullptr;
+        }
+        if (gepp_event != nullptr) {
+          e = hipStreamWaitEvent(st, gepp_event, 0);
+          if (e != hipSuccess) return e;
+          gepp_event = nullptr;
+        }
+        next_panel = panel_buf((pidx + 1) & 1);
+        const double* near = A + k0 * lda + k0 + bw;     // panel row 0 of these columns
+        GemmArgs sc{(int)(m - bw), (int)n_near, bw, yrest, b, near, lda, next_panel, b, -1.0,
+                    1.0, &stats->max_abs_W, nullptr, schur, sel(), near, lda, srcmap(), (int)m};
+        {
+          PhaseScope ps(5, st);
+          e = launch_gemm(sc, st);
+        }
+        if (e != hipSuccess) return e;
         ev_near = side_event();
         e = hipEventRecord(ev_near, st);
         if (e != hipSuccess) return e;
-      }
-      if (side != nullptr && nr > n_near) {
-        e = hipStreamWaitEvent(side, ev_moved, 0);
-        if (e != hipSuccess) return e;
-        // the far columns move on this stream, right before their update
-        MoveArgs mf{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, nullptr, nullptr, b,
-                    k0 + bw + n_near, n, n, 0};
-        {
-          PhaseScope ps(2, side);
-          e = launch_moves(mf, side);
+        if (nr > n_near) {
+          e = hipStreamWaitEvent(side, ev_sel, 0);
+          if (e != hipSuccess) return e;
+          MoveArgs mf{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, nullptr, nullptr, b,
+                      k0 + bw + n_near, n, n, 0, 0};
+          {
+            PhaseScope ps(2, side);
+            e = launch_moves(mf, side);
+          }
+          if (e != hipSuccess) return e;
+          GemmArgs sc_far{(int)(m - bw), (int)(nr - n_near), bw, yrest, b, a12 + n_near, lda,
+                          a22 + n_near, lda, -1.0, 1.0, &stats->max_abs_W, nullptr, schur};
+          {
+            PhaseScope ps(5, side);
+            e = launch_gemm(sc_far, side);
+          }
+          if (e != hipSuccess) return e;
+          ev_far = side_event();
+          e = hipEventRecord(ev_far, side);
+          if (e != hipSuccess) return e;
+          far_event = ev_far;
         }
-        if (e != hipSuccess) return e;
-        GemmArgs sc_far{(int)(m - bw), (int)(nr - n_near), bw, yrest, b, a12 + n_near, lda,
-                        a22 + n_near, lda, -1.0, 1.0, &stats->max_abs_W, nullptr, schur};
-        {
-          PhaseScope ps(5, side);
-          e = launch_gemm(sc_far, side);
-        }
-        if (e != hipSuccess) return e;
-        ev_far = side_event();
-        e = hipEventRecord(ev_far, side);
-        if (e != hipSuccess) return e;
-        far_event = ev_far;
       }
-    }
-    // ---- GEPP path
-    if (la) {
-      e = hipStreamWaitEvent(gs, ev_moved, 0);
+      // ---- GEPP path
+      e = hipStreamWaitEvent(gs, ev_sel, 0);
       if (e != hipSuccess) return e;
-      // the columns left of the panel and perm move on this stream
       if (k0 > 0 || perm != nullptr) {
-        MoveArgs ml{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, nullptr, b, 0, k0, n, 0};
+        MoveArgs ml{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, nullptr, b, 0, k0, n, 0, 0};
         {
           PhaseScope ps(2, gs);
           e = launch_moves(ml, gs);
@@ -455,6 +480,11 @@ struct Ctx {
       e = launch_gepp(ga, gs);
     }
     if (e != hipSuccess) return e;
+    if (la) {
+      gepp_event = side_event();
+      e = hipEventRecord(gepp_event, gs);
+      if (e != hipSuccess) return e;
+    }
     PermTopArgs pt{A, lda, k0, bw, perm, p11()};
     {
       PhaseScope ps(1, gs);
@@ -463,19 +493,27 @@ struct Ctx {
     if (e != hipSuccess) return e;
     if (m > bw) {
       // L21 = M^T (Pi11 L11)
-      GemmArgs l21{(int)(m - bw), bw, bw, Yp + (size_t)bw * b, b, PL(), bw,
-                   A + (k0 + bw) * lda + k0, lda, 1.0, 0.0, nullptr, nullptr, PRRP_FP64};
+      GemmArgs l21{(int)(m - bw), bw, bw, yrest, b, PL(), bw, A + (k0 + bw) * lda + k0, lda, 1.0,
+                   0.0, nullptr, nullptr, PRRP_FP64};
       {
         PhaseScope ps(3, gs);
         e = launch_gemm(l21, gs);
       }
       if (e != hipSuccess) return e;
-      if (side2 != nullptr) {
-        // the strong RRQR two panels on reuses this panel's sel and Y
+      if (la) {
+        // top rows of the next panel's columns, once the near update has read them
+        e = hipStreamWaitEvent(gs, ev_near, 0);
+        if (e != hipSuccess) return e;
+        MoveArgs mt{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, nullptr, nullptr, b,
+                    k0 + bw, k0 + bw + n_near, n, 0, 1};
+        {
+          PhaseScope ps(2, gs);
+          e = launch_moves(mt, gs);
+        }
+        if (e != hipSuccess) return e;
+        // the last reads of this panel's sel, Y and moves
         l21_hist[pidx & 1] = side_event();
         e = hipEventRecord(l21_hist[pidx & 1], gs);
-        if (e != hipSuccess) return e;
-        e = hipStreamWaitEvent(gs, ev_near, 0);
         if (e != hipSuccess) return e;
         if (ev_far != nullptr) {
           e = hipStreamWaitEvent(gs, ev_far, 0);
@@ -488,6 +526,13 @@ struct Ctx {
       }
       if (e != hipSuccess) return e;
     }
+    if (la && m == bw) {
+      // the strong RRQR two panels on reuses this panel's sel, Y and moves
+      l21_hist[pidx & 1] = side_event();
+      e = hipEventRecord(l21_hist[pidx & 1], gs);
+      if (e != hipSuccess) return e;
+    }
+    panel_src = next_panel;
     ++pidx;
     return hipSuccess;
   }
@@ -501,6 +546,8 @@ SrrqrArgs base_args(Ctx& c, int64_t k0, int bw) {
   a.k0 = k0;
   a.bw = bw;
   a.ldy = c.b;
+  a.panel = c.panel_src;
+  a.ldp = c.b;
   return a;
 }
 
@@ -577,6 +624,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
       a.record_block_L = 1;
       a.sel_out = c.sel();
       a.Y = (m > bw) ? c.Y() : nullptr;
+      if (c.side2 != nullptr) { a.plan_mv = c.mv(); a.srcmap = c.srcmap(); }
       PRRP_TRY(c.srrqr(a));
     } else {
       // ---------------------------------------------- tournament (Sec. 3.1)
@@ -652,6 +700,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
       r.record_block_L = 1;
       r.sel_out = c.sel();
       r.Y = c.Y();
+      if (c.side2 != nullptr) { r.plan_mv = c.mv(); r.srcmap = c.srcmap(); }
       PRRP_TRY(c.srrqr(r));
     }
     PRRP_TRY(c.finish_panel(k0, bw));

@@ -13,6 +13,10 @@
 // way into LDS and use v_mfma_f32_16x16x4f32 / v_mfma_f32_16x16x32_bf16 with
 // FP32 accumulation; C stays FP64.
 //
+// The update of the next panel's columns gathers: rows of B through a row
+// list (the selected rows, before the moves of Pi_j) and rows of C_in through
+// another (the rows that land at each position), writing C out of place.
+//
 // MFMA 16x16 operand layout (wave64): A operand lane l holds A[l%16][k-group
 // l/16], B operand lane l holds B[k-group l/16][l%16].  The 4 accumulator
 // values of lane l are D[4*(l/16) + v][l%16] for the FP32-accumulating
@@ -87,10 +91,13 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int bx, int by) {
       ra[v] = (gr < M && gk < K) ? g.A[(int64_t)gr * g.lda + gk] : 0.0;
     }
     const int gk = k0 + b_k;
+    const int64_t brow =
+        (gk < K) ? (g.b_rows ? (int64_t)min(max(g.b_rows[gk], 0), g.gather_rows - 1) : (int64_t)gk)
+                 : 0;
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
       const int gc = n0 + b_n + v;
-      rb[v] = (gk < K && gc < N) ? g.B[(int64_t)gk * g.ldb + gc] : 0.0;
+      rb[v] = (gk < K && gc < N) ? g.B[brow * g.ldb + gc] : 0.0;
     }
   };
   auto store_slab = [&](int buf) {
@@ -186,7 +193,10 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int bx, int by) {
         if (r < M && c < N) {
           const double p = (sizeof(T) == 8) ? accd[i][j][v] : (double)accf[i][j][v];
           double* cp = g.C + (int64_t)r * g.ldc + c;
-          const double val = (g.beta != 0.0) ? fma(g.alpha, p, g.beta * *cp) : g.alpha * p;
+          const double* cin =
+              g.Cin ? g.Cin + (int64_t)min(max(g.c_rows[r], 0), g.gather_rows - 1) * g.ldcin + c
+                    : cp;
+          const double val = (g.beta != 0.0) ? fma(g.alpha, p, g.beta * *cin) : g.alpha * p;
           *cp = val;
           amax = fmax(amax, fabs(val));
         }

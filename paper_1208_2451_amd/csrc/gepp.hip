@@ -67,7 +67,8 @@ __device__ __forceinline__ void gepp_body(const GeppArgs& a) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int i = ty + 16 * u;
-      const double* src = a.A + (a.k0 + (i < bw ? ssel[i] : 0)) * a.lda + a.k0;
+      const int64_t sr = i < bw ? min(max(ssel[i], 0), a.m - 1) : 0;
+      const double* src = a.panel ? a.panel + sr * a.ldp : a.A + (a.k0 + sr) * a.lda + a.k0;
 #pragma unroll
       for (int w = 0; w < 8; ++w) {
         const int c = tx + 16 * w;
@@ -401,7 +402,8 @@ constexpr int kStrip = 32;
 __device__ __forceinline__ void moves_body(const MoveArgs& a, int bx, int nbx) {
   __shared__ double buf[2 * kMaxB][kStrip];
   __shared__ int64_t pbuf[2 * kMaxB];
-  const int nm = *a.n_moves;
+  const int nm = min(a.top_only ? min(*a.n_moves, a.bw) : *a.n_moves, 2 * kMaxB);
+  const int lim = (int)(a.n - a.k0 - 1);       // entries are panel rows: clamp into the panel
   const int tid = threadIdx.x;
   const int64_t span = (a.c_end - a.c_begin) - a.skip_w;   // columns to move
   const int64_t c0 = (int64_t)bx * kStrip;
@@ -415,7 +417,7 @@ __device__ __forceinline__ void moves_body(const MoveArgs& a, int bx, int nbx) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = t0 + u * (kMoveThreads / kStrip);
-      v[u] = (cvalid && t < nm) ? a.A[(a.k0 + a.mv_src[t]) * a.lda + col] : 0.0;
+      v[u] = (cvalid && t < nm) ? a.A[(a.k0 + min(max(a.mv_src[t], 0), lim)) * a.lda + col] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -424,13 +426,14 @@ __device__ __forceinline__ void moves_body(const MoveArgs& a, int bx, int nbx) {
     }
   }
   if (bx == 0 && a.perm) {
-    for (int t = tid; t < nm; t += kMoveThreads) pbuf[t] = a.perm[a.k0 + a.mv_src[t]];
+    for (int t = tid; t < nm; t += kMoveThreads) pbuf[t] = a.perm[a.k0 + min(max(a.mv_src[t], 0), lim)];
   }
   __syncthreads();
   for (int t = r8; t < nm; t += kMoveThreads / kStrip)
-    if (cvalid && a.mv_dst[t] != a.mv_src[t]) a.A[(a.k0 + a.mv_dst[t]) * a.lda + col] = buf[t][cc];
+    if (cvalid && a.mv_dst[t] != a.mv_src[t])
+      a.A[(a.k0 + min(max(a.mv_dst[t], 0), lim)) * a.lda + col] = buf[t][cc];
   if (bx == 0 && a.perm) {
-    for (int t = tid; t < nm; t += kMoveThreads) a.perm[a.k0 + a.mv_dst[t]] = pbuf[t];
+    for (int t = tid; t < nm; t += kMoveThreads) a.perm[a.k0 + min(max(a.mv_dst[t], 0), lim)] = pbuf[t];
   }
   // Y rows: displaced rows (moves past the top block) carry their M columns;
   // spread over the workgroups, loads of a batch issued before its stores
@@ -444,13 +447,13 @@ __device__ __forceinline__ void moves_body(const MoveArgs& a, int bx, int nbx) {
       for (int u = 0; u < 8; ++u) {
         const int64_t e = e0 + u * stride;
         const int t = a.bw + (int)(e / a.bw), c = (int)(e % a.bw);
-        v[u] = (e < total) ? a.Y[(int64_t)a.mv_src[t] * a.ldy + c] : 0.0;
+        v[u] = (e < total) ? a.Y[(int64_t)min(max(a.mv_src[t], 0), lim) * a.ldy + c] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int64_t e = e0 + u * stride;
         const int t = a.bw + (int)(e / a.bw), c = (int)(e % a.bw);
-        if (e < total) a.Y[(int64_t)a.mv_dst[t] * a.ldy + c] = v[u];
+        if (e < total) a.Y[(int64_t)min(max(a.mv_dst[t], 0), lim) * a.ldy + c] = v[u];
       }
     }
   }

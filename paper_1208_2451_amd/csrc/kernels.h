@@ -60,6 +60,16 @@ struct SrrqrArgs {
   prrp_stats* stats;
   uint32_t* abort_flag;
   const SrrqrProblem* probs;  // nullable: batched launch, one problem per group
+  // Panel rows read from `panel` (row r at panel + r * ldp) instead of A.
+  const double* panel;        // nullable
+  int64_t ldp;
+  // Final selection of a single whole-panel tile (ngroups 1, no row_list):
+  // the kernel also forms the row moves of Pi_j (dst [0, 2 kMaxB), src
+  // [2 kMaxB, 4 kMaxB), count at [4 kMaxB]), writes the rows of M^T at their
+  // positions after the moves, and srcmap[r - bw] = the panel row that lands
+  // at position r >= bw.
+  int32_t* plan_mv;           // nullable
+  int32_t* srcmap;
 };
 hipError_t launch_srrqr(const SrrqrArgs& a, hipStream_t stream);
 size_t srrqr_smem_bytes(int bw);
@@ -80,6 +90,8 @@ struct GeppArgs {
   int32_t* n_moves;
   prrp_stats* stats;
   int32_t* p11;               // [bw] GEPP output: slot of the row at each final position
+  const double* panel;        // nullable: panel rows read from here (row r at panel + r * ldp)
+  int64_t ldp;
 };
 // Moves of Pi_j^T from the selection (sel, bw -> mv_dst, mv_src, n_moves).
 hipError_t launch_plan(const GeppArgs& a, hipStream_t stream);
@@ -117,6 +129,7 @@ struct MoveArgs {
   int64_t c_begin, c_end;     // columns moved: [c_begin, c_end) except the
   int64_t skip_lo;            //   skip_w columns from skip_lo
   int skip_w;
+  int top_only;               // only the moves into the top bw positions
 };
 hipError_t launch_moves(const MoveArgs& a, hipStream_t stream);
 
@@ -155,6 +168,13 @@ struct GemmArgs {
   double* amax;               // nullable: max |C_new| recorded here
   double* amax2;              // nullable: and here
   int prec;
+  const int32_t* b_rows;      // nullable: row k of B is B + b_rows[k] * ldb
+  // nullable: C_new = alpha A B + beta C_in written to C, row r of C_in at
+  // Cin + c_rows[r] * ldcin (gathered rows; C_in and C never overlap)
+  const double* Cin;
+  int64_t ldcin;
+  const int32_t* c_rows;
+  int gather_rows;            // gathered row indices are clamped into [0, gather_rows)
 };
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream);
 hipError_t launch_gemm_batched(const GemmArgs* list, int count, int max_m, int max_n, int prec,

@@ -62,6 +62,7 @@ struct Smem {
   double* vw;      // [waves][2 kMaxB] per-wave reflector vectors
   int* flags;      // [8]   0: abort, 1: rank deficient, 2: winner slot,
                    //       3: exchange slot, 4: failed wait of the key poll
+  int* dest;       // [kMaxB] position after Pi_j of each top-block row left out
 };
 
 }  // namespace
@@ -69,7 +70,7 @@ struct Smem {
 size_t srrqr_smem_bytes(int bw) {
   return sizeof(double) * (size_t)(bw * (bw + 1) / 2 + 4 * kMaxB + 8) +
          sizeof(double) * (size_t)(kThreads / 64) * 2 * kMaxB + sizeof(uint64_t) * 16 +
-         sizeof(int) * (kMaxB + 8);
+         sizeof(int) * (2 * kMaxB + 8);
 }
 
 // Words a post of a panel of width bw may have written: key, slot and the
@@ -95,6 +96,7 @@ void srrqr_kernel(SrrqrArgs a) {
   S.red = reinterpret_cast<uint64_t*>(S.vw + (kThreads / 64) * 2 * kMaxB);
   S.selpos = reinterpret_cast<int*>(S.red + 16);
   S.flags = S.selpos + kMaxB;
+  S.dest = S.flags + 8;
 
   const int G = a.G;
   const int g = blockIdx.x / G;
@@ -176,7 +178,7 @@ void srrqr_kernel(SrrqrArgs a) {
     chosen[q] = false;
     int64_t prow_idx = 0;
     if (live[q]) prow_idx = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + tpos[q];
-    const double* src = pA + (pk0 + prow_idx) * plda + pk0;
+    const double* src = a.panel ? a.panel + prow_idx * a.ldp : pA + (pk0 + prow_idx) * plda + pk0;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       const int c = l8 + 8 * k;
@@ -349,11 +351,25 @@ void srrqr_kernel(SrrqrArgs a) {
     if (S.flags[0]) break;
   }
 
-  if (S.flags[0]) {
+  // After a failed wait the launch's outputs are not formed; in-range
+  // placeholders keep the kernels that read them inside the panel.
+  auto abandon = [&]() {
     if (tid == 0) {
       set_info(pst, -2);
       st_dev_u32(a.abort_flag, 1u);
     }
+    if (psel && w == 0 && tid < bw && tlen > 0) {
+      const int t = min(tid, tlen - 1);
+      psel[tid] = a.row_list ? a.row_list[tstart + t] : tstart + t;
+    }
+    if (a.plan_mv) {
+      if (w == 0 && tid == 0) a.plan_mv[4 * kMaxB] = 0;
+      for (int t = row0 + tid; t < row0 + nloc; t += kThreads)
+        if (t >= bw) a.srcmap[t - bw] = t;
+    }
+  };
+  if (S.flags[0]) {
+    abandon();
     return;
   }
 
@@ -367,9 +383,11 @@ void srrqr_kernel(SrrqrArgs a) {
     // ============================================= M = R11^-1 R12 per row
     if (tid < bw) S.rdiag[tid] = 1.0 / S.R[tid * (tid + 1) / 2 + tid];
     __syncthreads();
+    // (the column block kk is unrolled so that every index into x is static;
+    // the 8 columns of a block stay a loop)
 #pragma unroll
     for (int kk = CPT - 1; kk >= 0; --kk) {
-#pragma unroll
+#pragma unroll 1
       for (int li = 7; li >= 0; --li) {
         const int i = 8 * kk + li;
         if (i >= bw) continue;
@@ -528,20 +546,93 @@ void srrqr_kernel(SrrqrArgs a) {
         __syncthreads();
       }
       if (S.flags[0]) {
-        if (tid == 0) { set_info(pst, -2); st_dev_u32(a.abort_flag, 1u); }
+        abandon();
         return;
       }
     }
+  }
 
-    // ----------------------------------------------- outputs: Y rows, max|M|
+  // ------------------------------------------- moves of Pi_j (whole panel)
+  // Pi_j is the sequence of interchanges of positions s and (position of
+  // slot s's row) for s = 0 .. bw-1.  Rows outside the top block move only
+  // when selected, so (i) slot s's row sits at Q[s] = sel[s] when step s
+  // comes, unless sel[s] < s: then it left position sel[s] at step sel[s]
+  // for Q[sel[s]], and so on, and Q[s] is the first position >= s on that
+  // chain; (ii) a top-block row u left out moves at step u to Q[u], and on
+  // along Q until it leaves the top block.  Both chains only increase, so the
+  // rounds below end; an unresolved entry waits for the entries it reads.
+  const bool fused = a.plan_mv != nullptr;
+  if (fused && w * a.rpw < bw) {             // workgroups holding top-block rows
+    if (wave == 0) {
+      const int e0 = lane, e1 = lane + 64;
+      const int s0 = e0 < bw ? S.selpos[e0] : 0;
+      const int s1 = e1 < bw ? S.selpos[e1] : 0;
+      if (e0 < bw) S.dest[e0] = -1;
+      if (e1 < bw) S.dest[e1] = -1;
+      if (e0 < bw && s0 < bw) S.dest[s0] = e0;   // selected: not moved out
+      if (e1 < bw && s1 < bw) S.dest[s1] = e1;
+      // Q by rounds; an unresolved entry holds -1 - (its chase position)
+      int v0 = e0 < bw ? (s0 >= e0 ? s0 : -1 - s0) : 0;
+      int v1 = e1 < bw ? (s1 >= e1 ? s1 : -1 - s1) : 0;
+      for (int it = 0; it <= bw * bw; ++it) {
+        if (!__any(v0 < 0 || v1 < 0)) break;
+        const int c0 = v0 < 0 ? -1 - v0 : 0;
+        const int c1 = v1 < 0 ? -1 - v1 : 0;
+        const int a0 = __shfl(v0, c0 & 63, 64), b0 = __shfl(v1, c0 & 63, 64);
+        const int a1 = __shfl(v0, c1 & 63, 64), b1 = __shfl(v1, c1 & 63, 64);
+        const int q0 = c0 < 64 ? a0 : b0, q1 = c1 < 64 ? a1 : b1;
+        if (v0 < 0 && q0 >= 0) v0 = (q0 >= e0) ? q0 : -1 - q0;
+        if (v1 < 0 && q1 >= 0) v1 = (q1 >= e1) ? q1 : -1 - q1;
+      }
+      const bool d0 = e0 < bw && S.dest[e0] == -1;
+      const bool d1 = e1 < bw && S.dest[e1] == -1;
+      int p0 = e0, p1 = e1;
+      for (int it = 0; it <= bw; ++it) {
+        const bool m0 = d0 && p0 < bw, m1 = d1 && p1 < bw;
+        if (!__any(m0 || m1)) break;
+        const int a0 = __shfl(v0, p0 & 63, 64), b0 = __shfl(v1, p0 & 63, 64);
+        const int a1 = __shfl(v0, p1 & 63, 64), b1 = __shfl(v1, p1 & 63, 64);
+        if (m0) p0 = p0 < 64 ? a0 : b0;
+        if (m1) p1 = p1 < 64 ? a1 : b1;
+      }
+      if (d0) S.dest[e0] = p0;
+      if (d1) S.dest[e1] = p1;
+      if (w == 0) {
+        // top positions take the selected rows in slot order, then the rows
+        // left out, in row order
+        int32_t* mv = a.plan_mv;
+        if (e0 < bw) { mv[e0] = e0; mv[2 * kMaxB + e0] = s0; }
+        if (e1 < bw) { mv[e1] = e1; mv[2 * kMaxB + e1] = s1; }
+        const uint64_t m0 = __ballot(d0), m1 = __ballot(d1);
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        const int n0 = __popcll(m0);
+        if (d0) {
+          const int k = bw + __popcll(m0 & below);
+          mv[k] = p0; mv[2 * kMaxB + k] = e0;
+        }
+        if (d1) {
+          const int k = bw + n0 + __popcll(m1 & below);
+          mv[k] = p1; mv[2 * kMaxB + k] = e1;
+        }
+        if (lane == 0) mv[4 * kMaxB] = bw + n0 + __popcll(m1);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ----------------------------------------------- outputs: Y rows, max|M|
+  // (at the rows' positions after Pi_j when the moves were formed here)
+  if (need_m && !rank_def && tlen > bw) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       if (live[q] && !chosen[q]) {
-        const int64_t pr = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + tpos[q];
+        const int t = (fused && tpos[q] < bw) ? S.dest[tpos[q]] : tpos[q];
+        const int64_t pr = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + t;
+        const bool in = t >= 0 && t < tlen;
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
           const int c = l8 + 8 * k;
-          if (c < bw) {
+          if (c < bw && in) {
             mmax_local = fmax(mmax_local, fabs(x[q][k]));
             if (pY) pY[pr * pldy + c] = x[q][k];
           }
@@ -554,10 +645,20 @@ void srrqr_kernel(SrrqrArgs a) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       if (live[q] && !chosen[q]) {
-        const int64_t pr = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + tpos[q];
+        const int t = (fused && tpos[q] < bw) ? S.dest[tpos[q]] : tpos[q];
+        const int64_t pr = a.row_list ? a.row_list[tstart + tpos[q]] : tstart + t;
 #pragma unroll
         for (int k = 0; k < CPT; ++k)
-          if (l8 + 8 * k < bw) pY[pr * pldy + l8 + 8 * k] = 0.0;
+          if (l8 + 8 * k < bw && t >= 0 && t < tlen) pY[pr * pldy + l8 + 8 * k] = 0.0;
+      }
+    }
+  }
+  if (fused && tlen > bw) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (live[q] && !chosen[q] && l8 == 0) {
+        const int t = tpos[q] < bw ? S.dest[tpos[q]] : tpos[q];
+        if (t >= bw && t < tlen) a.srcmap[t - bw] = tpos[q];
       }
     }
   }
