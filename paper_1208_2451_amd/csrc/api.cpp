@@ -73,8 +73,8 @@ Tiles tile_bounds(int64_t m, int64_t tile_rows, int b) {
 // whose latency grows with the number of workgroups polled (~1.8 us at 64,
 // ~3.3 us at 256 on MI355X), while fewer workgroups mean more rows each (at
 // most 128, the register budget).  Default: at most 64 rows per workgroup,
-// at most PRRP_PANEL_WGS (default 64, the CUs the look-ahead keeps free of
-// the trailing update) workgroups; none left without rows.
+// at most PRRP_PANEL_WGS (default 64, within the CUs the look-ahead keeps
+// free of the trailing update) workgroups; none left without rows.
 int panel_wg_cap() {
   static int cap = 0;
   if (cap == 0) {
@@ -149,16 +149,21 @@ inline int herr(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
 
 // ------------------------------------------------ look-ahead side stream
 // The far part of each Schur update runs on a side stream whose CU mask
-// leaves PRRP_RESERVE_CUS (default 64) CUs free, so that the next panel's
-// latency-bound kernels (strong RRQR, GEPP) on the caller's stream always
-// find free CUs and run concurrently with it.
+// leaves PRRP_RESERVE_CUS (default 96, 12 per XCD) CUs free, so that the
+// next panel's latency-bound kernels (strong RRQR, GEPP) always find free CUs
+// and run concurrently with it.  Measured at n = 8192, b = 128: reserving 96
+// rather than 64 CUs costs the far update little and shortens the panel chain
+// (its cross-workgroup exchanges meet less memory traffic).
 struct SideStream {
   int dev = -1;
   hipStream_t s = nullptr;
-  hipStream_t main = nullptr;   // non-blocking stream carrying the panel chain
+  hipStream_t main = nullptr;   // panel chain of LU_PRRP, on the reserved CUs
+  hipStream_t main_any = nullptr;   // panel chain of CALU_PRRP: a tournament level
+                                    // may hold more workgroups than the reserve
   hipStream_t s2 = nullptr;     // GEPP / L21 / U12 of finished panels
   hipEvent_t ev[64] = {};
   int next = 0;
+  int main_cus = 0;             // CUs `main` is confined to (0: all)
 };
 SideStream g_side;
 
@@ -180,7 +185,7 @@ hipError_t side_stream(hipStream_t* out) {
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  int reserve = env ? atoi(env) : 64;
+  int reserve = env ? atoi(env) : 96;
   if (reserve < 0) reserve = 0;
   if (reserve > cus / 2) reserve = cus / 2;
   std::vector<uint32_t> mask((cus + 31) / 32, 0u);
@@ -195,7 +200,23 @@ hipError_t side_stream(hipStream_t* out) {
     e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e != hipSuccess) return e;
   }
-  e = hipStreamCreateWithFlags(&g_side.main, hipStreamNonBlocking);
+  // The panel chain keeps to the reserved CUs (PRRP_MAIN_MASK=0: anywhere),
+  // so its persistent strong-RRQR workgroups never share a SIMD with the far
+  // update.  The mask interleaves over the XCDs, so every XCD keeps
+  // reserve / 8 CUs for it.
+  const char* em = getenv("PRRP_MAIN_MASK");
+  const bool main_mask = reserve > 0 && !(em && atoi(em) == 0);
+  std::vector<uint32_t> mmask((cus + 31) / 32, 0u);
+  for (int c = cus - reserve; c < cus; ++c) mmask[c / 32] |= 1u << (c % 32);
+  g_side.main_cus = 0;
+  if (main_mask &&
+      hipExtStreamCreateWithCUMask(&g_side.main, (uint32_t)mmask.size(), mmask.data()) == hipSuccess) {
+    g_side.main_cus = reserve;
+  } else {
+    e = hipStreamCreateWithFlags(&g_side.main, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  e = hipStreamCreateWithFlags(&g_side.main_any, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
   e = hipStreamCreateWithFlags(&g_side.s2, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
@@ -586,9 +607,14 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
     hipEvent_t e0 = side_event();
     PRRP_TRY(hipEventRecord(e0, caller));
     PRRP_TRY(hipStreamWaitEvent(c.side, e0, 0));
-    PRRP_TRY(hipStreamWaitEvent(g_side.main, e0, 0));
+    // every workgroup of a strong-RRQR launch must be resident at once: one
+    // LU_PRRP panel (at most 64) fits the reserved CUs, a CALU_PRRP
+    // tournament level need not
+    const bool fits = g_side.main_cus == 0 || panel_wg_cap() <= g_side.main_cus;
+    hipStream_t chain = (method == 0 && fits) ? g_side.main : g_side.main_any;
+    PRRP_TRY(hipStreamWaitEvent(chain, e0, 0));
     PRRP_TRY(hipStreamWaitEvent(g_side.s2, e0, 0));
-    c.st = g_side.main;
+    c.st = chain;
     c.side2 = g_side.s2;
   }
   int height = 0;
