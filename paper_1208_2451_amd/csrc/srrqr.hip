@@ -182,7 +182,7 @@ void srrqr_kernel(SrrqrArgs a) {
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       const int c = l8 + 8 * k;
-      x[q][k] = (live[q] && c < bw) ? src[c] : 0.0;
+      x[q][k] = (live[q] && c < bw) ? ld_g(src + c) : 0.0;
     }
   }
   if (tid < kMaxB) { S.vsh[tid] = 0.0; }
@@ -350,6 +350,8 @@ void srrqr_kernel(SrrqrArgs a) {
     __syncthreads();
     if (S.flags[0]) break;
   }
+  // the last pass wrote R's last column (wave 1) and no barrier followed it
+  __syncthreads();
 
   // After a failed wait the launch's outputs are not formed; in-range
   // placeholders keep the kernels that read them inside the panel.
@@ -634,7 +636,7 @@ void srrqr_kernel(SrrqrArgs a) {
           const int c = l8 + 8 * k;
           if (c < bw && in) {
             mmax_local = fmax(mmax_local, fabs(x[q][k]));
-            if (pY) pY[pr * pldy + c] = x[q][k];
+            if (pY) st_g(pY + pr * pldy + c, x[q][k]);
           }
         }
       }
