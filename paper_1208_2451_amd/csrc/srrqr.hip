@@ -273,8 +273,11 @@ void srrqr_kernel(SrrqrArgs a) {
       uint64_t gkey = wkey;
       uint64_t* post_r = slots + (size_t)s * round_stride;
       if (multi) {
-        // post my candidate: the owner's 8 lanes write the row (all 8 CPT
-        // words fit the post's width; words past bw are never read), then the key
+        // post my candidate: the key first (it travels while the row is
+        // written; readers poll every row word for itself), then the owner's
+        // 8 lanes write the row (all 8 CPT words fit the post's width; words
+        // past bw are never read)
+        if (tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
         int cq = -1;
 #pragma unroll
         for (int q = 0; q < RPT; ++q)
@@ -291,7 +294,6 @@ void srrqr_kernel(SrrqrArgs a) {
 #pragma unroll
           for (int k = 0; k < CPT; ++k) st_dev(dst + 8 * k, (uint64_t)__double_as_longlong(xv[k]));
         }
-        if (tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
         // wave 0 polls the G keys (one poller per workgroup keeps the fabric
         // traffic low) and shares the maximum through LDS
         if (wave == 0) {
