@@ -124,6 +124,14 @@ __device__ __forceinline__ uint64_t wave_max_key(uint64_t v) {
   return umax(umax(readlane_u64(v, 0), readlane_u64(v, 16)),
               umax(readlane_u64(v, 32), readlane_u64(v, 48)));
 }
+// The same when the 8 lanes of every row already hold one value (sum8 leaves
+// the same bits in all 8 lanes: each butterfly level adds the same two
+// operands in either order): only the 8 rows are compared.
+__device__ __forceinline__ uint64_t wave_max_rows(uint64_t v) {
+  v = umax(v, dpp_u64<0x140>(v));          // rows of 16
+  return umax(umax(readlane_u64(v, 0), readlane_u64(v, 16)),
+              umax(readlane_u64(v, 32), readlane_u64(v, 48)));
+}
 // Wave-wide sum in a fixed order (bitwise reproducible); wave-uniform result.
 __device__ __forceinline__ double wave_sum_fixed(double v) {
   v = sum8(v);

@@ -8,7 +8,7 @@
 
 namespace prrp {
 
-constexpr int kPostW = 2 + 128;   // words per posted candidate: key, slot, row
+constexpr int kPostW = 4 + 128;   // words per posted candidate: key, slot, row, alpha, beta
 constexpr int kMaxGroups = 256;   // tiles per srrqr launch
 
 // ------------------------------------------------------------ strong RRQR

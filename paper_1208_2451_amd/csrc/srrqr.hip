@@ -56,7 +56,7 @@ struct Smem {
   double* vsh;     // [kMaxB] reflector / exchange vector
   double* prow;    // [2 kMaxB] winner's row, zero past bw (unguarded reads)
   double* rdiag;   // [kMaxB] 1 / R(i,i)
-  double* scal;    // [8]   beta, gamma, ...
+  double* scal;    // [8]   4, 5: alpha, beta of the pivot row's reflector
   uint64_t* red;   // [16]  reduction scratch
   int* selpos;     // [kMaxB] tile positions in slot order
   double* vw;      // [waves][2 kMaxB] per-wave reflector vectors
@@ -73,12 +73,13 @@ size_t srrqr_smem_bytes(int bw) {
          sizeof(int) * (2 * kMaxB + 8);
 }
 
-// Words a post of a panel of width bw may have written: key, slot and the
-// row in whole blocks of 8 columns per lane (CPT rounded as in dispatch).
+// Words a post of a panel of width bw may have written: key, slot, the row
+// in whole blocks of 8 columns per lane (CPT rounded as in dispatch), then
+// the alpha and beta of the reflector the row defines.
 __device__ __forceinline__ int post_width(int bw) {
   int cpt = (bw + 7) / 8;
   cpt = cpt <= 2 ? (cpt <= 1 ? 1 : 2) : (cpt <= 4 ? 4 : (cpt <= 8 ? 8 : 16));
-  return 2 + 8 * cpt;
+  return 4 + 8 * cpt;
 }
 
 template <int CPT, int RPT>
@@ -206,13 +207,21 @@ void srrqr_kernel(SrrqrArgs a) {
       const int c0 = sp + lane, c1 = sp + lane + 64;
       const double x0 = S.prow[c0];           // zero past bw
       const double x1 = S.prow[c1];
-      const double tail = wave_sum_fixed((lane == 0 ? 0.0 : x0 * x0) + x1 * x1);  // c > sp
       const double head = S.prow[sp];
-      const double nrm = sqrt(fma(head, head, tail));
-      const double alpha = (nrm == 0.0) ? 0.0 : -copysign(nrm, head);
+      double alpha, beta;
+      if (a.mode == 0) {
+        // formed by the pivot row's owner while its key travelled
+        alpha = S.scal[4];
+        beta = S.scal[5];
+      } else {
+        const double tail = wave_sum_fixed((lane == 0 ? 0.0 : x0 * x0) + x1 * x1);  // c > sp
+        const double nrm = sqrt(fma(head, head, tail));
+        alpha = (nrm == 0.0) ? 0.0 : -copysign(nrm, head);
+        const double v00 = head - alpha;
+        const double vtv = fma(v00, v00, tail);
+        beta = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+      }
       const double v0 = head - alpha;
-      const double vtv = fma(v0, v0, tail);
-      const double beta = (vtv > 0.0) ? 2.0 / vtv : 0.0;
       if (wave == 1) {
         for (int i = lane; i < sp; i += 64) S.R[sp * (sp + 1) / 2 + i] = S.prow[i];
         if (lane == 0) S.R[sp * (sp + 1) / 2 + sp] = alpha;
@@ -227,23 +236,25 @@ void srrqr_kernel(SrrqrArgs a) {
       double vr[CPT];
 #pragma unroll
       for (int k = 0; k < CPT; ++k) vr[k] = vw[l8 + 8 * k];
+      // branch-free over the rows (so that their chains interleave); rows
+      // already chosen, and rows past the tile, take f = 0 and keep their values
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        if (live[q] && !chosen[q]) {
-          double dd[4] = {0.0, 0.0, 0.0, 0.0};     // independent chains
+        double dd[4] = {0.0, 0.0, 0.0, 0.0};     // independent chains
 #pragma unroll
-          for (int k = 0; k < CPT; ++k) dd[k & 3] = fma(vr[k], x[q][k], dd[k & 3]);
-          const double d = sum8((dd[0] + dd[1]) + (dd[2] + dd[3]));
-          const double f = beta * d;
+        for (int k = 0; k < CPT; ++k) dd[k & 3] = fma(vr[k], x[q][k], dd[k & 3]);
+        const double d = sum8((dd[0] + dd[1]) + (dd[2] + dd[3]));
+        const double f = (live[q] && !chosen[q]) ? beta * d : 0.0;
 #pragma unroll
-          for (int k = 0; k < CPT; ++k) x[q][k] = fma(-f, vr[k], x[q][k]);
-        }
+        for (int k = 0; k < CPT; ++k) x[q][k] = fma(-f, vr[k], x[q][k]);
       }
     }
     if (s == bw) break;
 
     int p;              // tile position of this step's pivot
     int wbad = 0;
+    int cq = -1;        // the workgroup's candidate among this thread's rows
+    double c_alpha = 0.0, c_beta = 0.0;   // the reflector it would define
     if (a.mode == 0) {
       uint64_t best = 0;
       // 0/1 masks of the trailing columns c >= s, shared by the rows (columns
@@ -252,6 +263,7 @@ void srrqr_kernel(SrrqrArgs a) {
 #pragma unroll
       for (int k = 0; k < CPT; ++k)
         cm[k] = __hiloint2double((l8 + 8 * k >= s) ? 0x3FF00000 : 0, 0);
+      double nuq[RPT];
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         double nn[4] = {0.0, 0.0, 0.0, 0.0};
@@ -260,11 +272,11 @@ void srrqr_kernel(SrrqrArgs a) {
           const double xm = x[q][k] * cm[k];
           nn[k & 3] = fma(xm, xm, nn[k & 3]);
         }
-        const double nu = sum8((nn[0] + nn[1]) + (nn[2] + nn[3]));
-        const uint64_t key = (live[q] && !chosen[q]) ? make_key(nu, (uint32_t)tpos[q]) : 0ull;
+        nuq[q] = sum8((nn[0] + nn[1]) + (nn[2] + nn[3]));
+        const uint64_t key = (live[q] && !chosen[q]) ? make_key(nuq[q], (uint32_t)tpos[q]) : 0ull;
         best = key > best ? key : best;
       }
-      best = wave_max_key(best);
+      best = wave_max_rows(best);
       if (lane == 0) S.red[wave] = best;
       __syncthreads();
       uint64_t wkey = S.red[0];
@@ -272,28 +284,45 @@ void srrqr_kernel(SrrqrArgs a) {
       for (int i = 1; i < kThreads / 64; ++i) wkey = umax(wkey, S.red[i]);
       uint64_t gkey = wkey;
       uint64_t* post_r = slots + (size_t)s * round_stride;
-      if (multi) {
-        // post my candidate: the key first (it travels while the row is
-        // written; readers poll every row word for itself), then the owner's
-        // 8 lanes write the row (all 8 CPT words fit the post's width; words
-        // past bw are never read)
-        if (tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
-        int cq = -1;
+      // Post my candidate: the key first (it travels while the rest is
+      // written; readers poll every word for itself), then the candidate's 8
+      // lanes write the row (all 8 CPT words fit the post's width; words past
+      // bw are never read) and the alpha, beta of the reflector it defines:
+      // nrm^2 is its trailing norm nu, alpha = -sign(head) nrm and
+      // beta = 2 / (v^T v) = 1 / (nrm (nrm + |head|)).
+      if (multi && tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
 #pragma unroll
-        for (int q = 0; q < RPT; ++q)
-          if (wkey != 0 && live[q] && !chosen[q] && (uint32_t)tpos[q] == key_index(wkey)) cq = q;
-        if (cq >= 0) {
-          double xv[CPT];
+      for (int q = 0; q < RPT; ++q)
+        if (wkey != 0 && live[q] && !chosen[q] && (uint32_t)tpos[q] == key_index(wkey)) cq = q;
+      if (cq >= 0) {
+        double xv[CPT];
 #pragma unroll
-          for (int k = 0; k < CPT; ++k) {
-            xv[k] = x[0][k];
+        for (int k = 0; k < CPT; ++k) {
+          xv[k] = x[0][k];
 #pragma unroll
-            for (int q = 1; q < RPT; ++q) xv[k] = (cq == q) ? x[q][k] : xv[k];
-          }
-          uint64_t* dst = post_r + (size_t)w * kPostW + 2 + l8;
+          for (int q = 1; q < RPT; ++q) xv[k] = (cq == q) ? x[q][k] : xv[k];
+        }
+        uint64_t* dst = post_r + (size_t)w * kPostW + 2 + l8;
+        if (multi) {
 #pragma unroll
           for (int k = 0; k < CPT; ++k) st_dev(dst + 8 * k, (uint64_t)__double_as_longlong(xv[k]));
         }
+        double xs = xv[0];                  // column s sits on lane s & 7
+#pragma unroll
+        for (int k = 1; k < CPT; ++k) xs = (k == (s >> 3)) ? xv[k] : xs;
+        const double head = __shfl(xs, (lane & ~7) | (s & 7), 64);
+        double nuv = nuq[0];
+#pragma unroll
+        for (int q = 1; q < RPT; ++q) nuv = (cq == q) ? nuq[q] : nuv;
+        const double nrm = sqrt(nuv);
+        c_alpha = (nrm == 0.0) ? 0.0 : -copysign(nrm, head);
+        c_beta = (nrm == 0.0) ? 0.0 : 1.0 / (nrm * (nrm + fabs(head)));
+        if (multi && l8 == 0) {
+          st_dev(dst + 8 * CPT, (uint64_t)__double_as_longlong(c_alpha));
+          st_dev(dst + 8 * CPT + 1, (uint64_t)__double_as_longlong(c_beta));
+        }
+      }
+      if (multi) {
         // wave 0 polls the G keys (one poller per workgroup keeps the fabric
         // traffic low) and shares the maximum through LDS
         if (wave == 0) {
@@ -341,10 +370,17 @@ void srrqr_kernel(SrrqrArgs a) {
           chosen[q] = true;
         }
       }
+      if (a.mode == 0 && cq >= 0 && l8 == 0) { S.scal[4] = c_alpha; S.scal[5] = c_beta; }
     } else if (owner < G) {
       if (tid < bw) {
         const uint64_t v = poll_word(post_r + (size_t)owner * kPostW + 2 + tid, a.abort_flag, &wbad);
         S.prow[tid] = __longlong_as_double((long long)v);
+      }
+      if (a.mode == 0 && tid >= kThreads - 2) {
+        const int j = tid - (kThreads - 2);
+        const uint64_t v =
+            poll_word(post_r + (size_t)owner * kPostW + 2 + 8 * CPT + j, a.abort_flag, &wbad);
+        S.scal[4 + j] = __longlong_as_double((long long)v);
       }
     }
     if (wbad) S.flags[0] = 1;
@@ -438,7 +474,7 @@ void srrqr_kernel(SrrqrArgs a) {
             if (rk > best) { best = rk; best_slot = (int)key_index(sk); }
           }
         }
-        const uint64_t wbest = wave_max_key(best);
+        const uint64_t wbest = wave_max_rows(best);
         if (lane == 0) S.red[wave] = wbest;
         __syncthreads();
         uint64_t wkey = S.red[0];
