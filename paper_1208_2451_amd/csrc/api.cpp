@@ -302,9 +302,10 @@ struct Ctx {
   hipStream_t side = nullptr;        // look-ahead stream (null: no look-ahead)
   hipStream_t side2 = nullptr;       // GEPP / L21 / U12 stream (null: no look-ahead)
   hipEvent_t far_event = nullptr;    // pending far Schur update on `side`
-  hipEvent_t l21_hist[2] = {};       // GEPP path of the last two panels (by parity)
   int pidx = 0;                      // panel index (parity of sel / Y)
-  hipEvent_t gepp_event = nullptr;   // GEPP of the previous panel (reads its panel buffer)
+  // The previous panel's GEPP path past its last reads of sel, Y, the moves
+  // and its panel buffer, and past the far update (which it waits for).
+  hipEvent_t join_event = nullptr;
   const double* panel_src = nullptr; // this panel's columns (null: in A)
 
   uint64_t* slot_set(int parity) {
@@ -363,17 +364,6 @@ struct Ctx {
     prev_rounds = a.rounds_out;
     ++launch_no;
     return e;
-  }
-
-  // Before a panel's strong RRQR: the GEPP path of the panel two steps back
-  // (same sel / Y buffers) must have finished reading them.
-  hipError_t before_panel() {
-    if (l21_hist[pidx & 1] != nullptr) {
-      hipError_t e = hipStreamWaitEvent(st, l21_hist[pidx & 1], 0);
-      l21_hist[pidx & 1] = nullptr;
-      return e;
-    }
-    return hipSuccess;
   }
 
   // Steps after the pivot rows of the panel at k0 are known (sel(), Y()).
@@ -437,17 +427,14 @@ struct Ctx {
       if (e != hipSuccess) return e;
       if (m > bw) {
         n_near = std::min<int64_t>(b, nr);
-        // the previous far update wrote these columns; the previous panel's
-        // GEPP read the buffer written here
-        if (far_event != nullptr) {
-          e = hipStreamWaitEvent(st, far_event, 0);
+        // One wait: the previous far update wrote these columns, the
+        // previous panel's GEPP read the buffer written here, and the strong
+        // RRQR of the next panel reuses the buffers (sel, Y, moves) of the
+        // panel before this one, whose readers all precede that event.
+        if (join_event != nullptr) {
+          e = hipStreamWaitEvent(st, join_event, 0);
           if (e != hipSuccess) return e;
-          far_event = nullptr;
-        }
-        if (gepp_event != nullptr) {
-          e = hipStreamWaitEvent(st, gepp_event, 0);
-          if (e != hipSuccess) return e;
-          gepp_event = nullptr;
+          join_event = nullptr;
         }
         next_panel = panel_buf((pidx + 1) & 1);
         const double* near = A + k0 * lda + k0 + bw;     // panel row 0 of these columns
@@ -501,11 +488,6 @@ struct Ctx {
       e = launch_gepp(ga, gs);
     }
     if (e != hipSuccess) return e;
-    if (la) {
-      gepp_event = side_event();
-      e = hipEventRecord(gepp_event, gs);
-      if (e != hipSuccess) return e;
-    }
     PermTopArgs pt{A, lda, k0, bw, perm, p11()};
     {
       PhaseScope ps(1, gs);
@@ -532,25 +514,18 @@ struct Ctx {
           e = launch_moves(mt, gs);
         }
         if (e != hipSuccess) return e;
-        // the last reads of this panel's sel, Y and moves
-        l21_hist[pidx & 1] = side_event();
-        e = hipEventRecord(l21_hist[pidx & 1], gs);
-        if (e != hipSuccess) return e;
         if (ev_far != nullptr) {
           e = hipStreamWaitEvent(gs, ev_far, 0);
           if (e != hipSuccess) return e;
         }
+        join_event = side_event();
+        e = hipEventRecord(join_event, gs);
+        if (e != hipSuccess) return e;
       }
       {
         PhaseScope ps(4, gs);
         e = launch_trsm_u12(A, lda, k0, bw, nr, &stats->max_abs_U, &stats->max_abs_W, p11(), gs);
       }
-      if (e != hipSuccess) return e;
-    }
-    if (la && m == bw) {
-      // the strong RRQR two panels on reuses this panel's sel, Y and moves
-      l21_hist[pidx & 1] = side_event();
-      e = hipEventRecord(l21_hist[pidx & 1], gs);
       if (e != hipSuccess) return e;
     }
     panel_src = next_panel;
@@ -635,7 +610,6 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
   for (int64_t k0 = 0; k0 < n; k0 += b) {
     const int bw = (int)std::min<int64_t>(b, n - k0);
     const int64_t m = n - k0;
-    PRRP_TRY(c.before_panel());
     Tiles t;
     if (method == 1) t = tile_bounds(m, tile_rows, bw);
     if (method == 0 || t.start.size() == 1) {
