@@ -15,6 +15,14 @@
  *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL is
  *     the default stream).  Argument errors are detected on the host before
  *     anything is enqueued and returned synchronously.
+ *   - A factorization with n > 2b runs its panels ahead of the trailing
+ *     update on streams of the library's own (created once per process on
+ *     the current device; the panel chain's stream is confined to
+ *     PRRP_RESERVE_CUS CUs, default 96, the far update's to the others).  It
+ *     starts after the work already enqueued on `stream`, and `stream` waits
+ *     for all of it, so to the caller it is one operation on `stream`.
+ *     Factorizations issued from several host threads are enqueued one at a
+ *     time on those streams.
  *   - The caller owns every buffer.  Factor and solve calls allocate no device
  *     memory: scratch space comes from a caller-provided `workspace` whose
  *     size is returned by the matching *_workspace_size query (a pure host

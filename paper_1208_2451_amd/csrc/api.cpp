@@ -18,6 +18,7 @@
 #include <type_traits>
 #include <vector>
 #include <cstdlib>
+#include <mutex>
 
 #include "common.h"
 #include "kernels.h"
@@ -574,7 +575,12 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
   c.L = make_layout(n, b, method, tile_rows);
   PRRP_TRY(srrqr_prepare());
   hipStream_t caller = c.st;
+  // The look-ahead streams and their event ring are shared by the process:
+  // one host thread at a time enqueues a factorization on them.
+  static std::mutex lookahead_mu;
+  std::unique_lock<std::mutex> lock(lookahead_mu, std::defer_lock);
   if (lookahead && lookahead_enabled() && n > 2 * b) {
+    lock.lock();
     // The panel chain runs on an internal non-blocking stream and the far
     // Schur updates on the side stream; both start after earlier work on the
     // caller's stream, which in turn waits for both at the end.
