@@ -265,11 +265,6 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream) {
   // hide the LDS and global latency between MFMA bursts (measured on MI355X:
   // FP64 16 -> 32 TFLOP/s, FP32 35 -> 52 TFLOP/s at 8064 x 7936 x 128).
   const int64_t big = (int64_t)((a.M + 127) / 128) * ((a.N + 127) / 128);
-  // The gathered update of the next panel's columns (K = b <= 128): 32-deep K
-  // slabs halve the staging rounds on its short critical-path launch; the MFMA
-  // sequence over k, hence every result bit, is the same as with 16.
-  if (a.Cin != nullptr && a.K <= 128 && big < 512 && a.prec == PRRP_FP64)
-    return launch_tiles<64, 64, 2, 2, 32>(a, stream);
   if (big >= 512) {
     if (a.prec == PRRP_FP64) return launch_tiles<128, 128, 4, 2, 16>(a, stream);
     return launch_tiles<128, 128, 4, 4, 16>(a, stream);
