@@ -397,7 +397,7 @@ struct Ctx {
     double* a22 = A + (k0 + bw) * lda + k0 + bw;
     const double* yrest = Yp + (size_t)bw * b;
     hipStream_t gs = la ? side2 : st;
-    hipEvent_t ev_sel = nullptr, ev_near = nullptr, ev_far = nullptr;
+    hipEvent_t ev_near = nullptr, ev_far = nullptr;
     int64_t n_near = nr;
     double* next_panel = nullptr;
     if (!la) {
@@ -423,9 +423,10 @@ struct Ctx {
         if (e != hipSuccess) return e;
       }
     } else {
-      ev_sel = side_event();
-      e = hipEventRecord(ev_sel, st);
-      if (e != hipSuccess) return e;
+      // One event on the panel chain per panel, after the near update (or
+      // after the strong RRQR when there is none): both side streams start
+      // from it, which keeps a second marker out of the critical path and
+      // costs them nothing (they finish well inside the next strong RRQR).
       if (m > bw) {
         n_near = std::min<int64_t>(b, nr);
         // One wait: the previous far update wrote these columns, the
@@ -446,11 +447,13 @@ struct Ctx {
           e = launch_gemm(sc, st);
         }
         if (e != hipSuccess) return e;
-        ev_near = side_event();
-        e = hipEventRecord(ev_near, st);
-        if (e != hipSuccess) return e;
+      }
+      ev_near = side_event();
+      e = hipEventRecord(ev_near, st);
+      if (e != hipSuccess) return e;
+      if (m > bw) {
         if (nr > n_near) {
-          e = hipStreamWaitEvent(side, ev_sel, 0);
+          e = hipStreamWaitEvent(side, ev_near, 0);
           if (e != hipSuccess) return e;
           MoveArgs mf{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, nullptr, nullptr, b,
                       k0 + bw + n_near, n, n, 0, 0};
@@ -473,7 +476,7 @@ struct Ctx {
         }
       }
       // ---- GEPP path
-      e = hipStreamWaitEvent(gs, ev_sel, 0);
+      e = hipStreamWaitEvent(gs, ev_near, 0);
       if (e != hipSuccess) return e;
       if (k0 > 0 || perm != nullptr) {
         MoveArgs ml{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, nullptr, b, 0, k0, n, 0, 0};
@@ -505,9 +508,7 @@ struct Ctx {
       }
       if (e != hipSuccess) return e;
       if (la) {
-        // top rows of the next panel's columns, once the near update has read them
-        e = hipStreamWaitEvent(gs, ev_near, 0);
-        if (e != hipSuccess) return e;
+        // top rows of the next panel's columns (the near update has read them)
         MoveArgs mt{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, nullptr, nullptr, b,
                     k0 + bw, k0 + bw + n_near, n, 0, 1};
         {
