@@ -425,8 +425,20 @@ struct Ctx {
     } else {
       // One event on the panel chain per panel, after the near update (or
       // after the strong RRQR when there is none): both side streams start
-      // from it, which keeps a second marker out of the critical path and
-      // costs them nothing (they finish well inside the next strong RRQR).
+      // from it, which keeps a second marker out of the critical path.  A far
+      // update long enough to outlast the next strong RRQR starts right after
+      // this one instead (an extra marker): at FP64, (m - b) x far columns
+      // above 36 M elements (72 M with FP32 / BF16 operands), measured at
+      // about 20 and 40 TFLOP/s against about 4.5 us per strong-RRQR step.
+      const int64_t nfar = (m > bw) ? nr - std::min<int64_t>(b, nr) : 0;
+      const double far_area = (double)(m - bw) * (double)nfar;
+      const bool far_early = nfar > 0 && far_area > ((schur == PRRP_FP64) ? 3.6e7 : 7.2e7);
+      hipEvent_t ev_sel = nullptr;
+      if (far_early) {
+        ev_sel = side_event();
+        e = hipEventRecord(ev_sel, st);
+        if (e != hipSuccess) return e;
+      }
       if (m > bw) {
         n_near = std::min<int64_t>(b, nr);
         // One wait: the previous far update wrote these columns, the
@@ -453,7 +465,7 @@ struct Ctx {
       if (e != hipSuccess) return e;
       if (m > bw) {
         if (nr > n_near) {
-          e = hipStreamWaitEvent(side, ev_near, 0);
+          e = hipStreamWaitEvent(side, far_early ? ev_sel : ev_near, 0);
           if (e != hipSuccess) return e;
           MoveArgs mf{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, nullptr, nullptr, b,
                       k0 + bw + n_near, n, n, 0, 0};
