@@ -432,7 +432,12 @@ struct Ctx {
       // about 20 and 40 TFLOP/s against about 4.5 us per strong-RRQR step.
       const int64_t nfar = (m > bw) ? nr - std::min<int64_t>(b, nr) : 0;
       const double far_area = (double)(m - bw) * (double)nfar;
-      const bool far_early = nfar > 0 && far_area > ((schur == PRRP_FP64) ? 3.6e7 : 7.2e7);
+      static const double early_area = [] {
+        const char* v = getenv("PRRP_FAR_EARLY_AREA");   // FP64 threshold, elements
+        return v ? atof(v) : 3.6e7;
+      }();
+      const bool far_early =
+          nfar > 0 && far_area > ((schur == PRRP_FP64) ? early_area : 2.0 * early_area);
       hipEvent_t ev_sel = nullptr;
       if (far_early) {
         ev_sel = side_event();
