@@ -29,9 +29,12 @@ tree stacks the running candidates over the next whole tile.
 Pinned by tests/test_oracle_lu.py (b = 1 equals LAPACK getrf, A[perm] = LU,
 |L_2j| <= tau, per-step growth bound, Wilkinson and Foster growth printed in
 the paper or given in closed form, CALU_PRRP with one tile equals LU_PRRP,
-node certificates and the per-step (1 + tau b)^(H+1) bound).  The growth 1
-printed for the Wright matrix is not used as a pin: with either reading of
-exp(M h) (exact, or its first-order form) the last pivot of U is 2.
+node certificates and the per-step (1 + tau b)^(H+1) bound), and by
+tests/test_oracle_exact_rules.py (the tournament against an exact-rational
+replay in which a node stacks its left child's candidates over its right
+child's).  The growth 1 printed for the Wright matrix and the 1.33 printed
+for CALU_PRRP on the Foster matrix are not pins: exact computations there
+show that no pivoting attains them.
 """
 from __future__ import annotations
 

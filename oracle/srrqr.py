@@ -21,7 +21,11 @@ Readings where the paper is silent:
 
 Pinned by tests/test_oracle_srrqr.py: brute-force greedy selection in exact
 rational arithmetic, LAPACK geqp3 order, Cramer-rule determinant checks of
-the final selection, and the |det R11| growth of every interchange.
+the final selection, and the |det R11| growth of every interchange; and by
+tests/test_oracle_exact_rules.py: every interchange, in order, against an
+exact-rational replay of the rule (largest Cramer ratio |det| growth, ties to
+the lowest row, then the lowest slot), on panels with and without duplicated
+rows.
 """
 from __future__ import annotations
 
@@ -44,6 +48,7 @@ class SRRQRResult:
     rank_deficient_step: int = -1   # first QRCP step with a zero residual
     qrcp_order: list = field(default_factory=list)
     det_ratios: list = field(default_factory=list)  # |det R11| growth per swap
+    swap_log: list = field(default_factory=list)    # (slot, row in, row out) per swap
 
     @property
     def max_abs_M(self) -> float:
@@ -123,6 +128,7 @@ def strong_rrqr(P: np.ndarray, tau: float, max_swaps: int | None = None) -> SRRQ
             raise RuntimeError("strong RRQR exchange did not terminate")
         res.det_ratios.append(abs(M[i, j]))
         out_row = sel[i]
+        res.swap_log.append((i, rest[j], out_row))
         sel[i] = rest[j]
         del rest[j]
         insort(rest, out_row)
