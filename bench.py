@@ -220,8 +220,9 @@ def main():
         def step():
             A.copy_(A0)
             r = prrp.factor(A, b, tau, precision=prec, workspace=ws)
-            X, it, rel = prrp.refine(A0, A, r.perm, B, tol=args.tol, max_iter=30, workspace=sws)
-            return r, X, it, rel
+            X, it, rel, status = prrp.refine(A0, A, r.perm, B, tol=args.tol, max_iter=30,
+                                             workspace=sws)
+            return r, X, it, rel, status
 
         for _ in range(args.warmup):
             step()
@@ -231,7 +232,7 @@ def main():
         for _ in range(args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r, X, it, rel = step()
+            r, X, it, rel, status = step()
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             iters.append(it)

@@ -35,7 +35,9 @@
  *     deterministically: magnitudes are compared on their binary64 encoding
  *     with the 19 low mantissa bits dropped, and the lowest current row index
  *     wins among equals (for an exchange: lowest row, then lowest slot).
- *   - Supported sizes: 1 <= n <= 2^19 - 2, 1 <= b <= 128, b <= n.
+ *   - Supported sizes: 1 <= n <= 2^19 - 2, 1 <= b <= 128, b <= n, and, for
+ *     LU_PRRP, n small enough that one panel's strong-RRQR workgroups fit
+ *     the device at once (prrp_panel_cus; about 65536 on MI355X).
  *
  * Factor output (in place, LAPACK convention): on exit A holds U on and above
  * the diagonal and the unit-lower L strictly below it (diagonal implied), and
@@ -81,6 +83,16 @@ typedef struct prrp_stats {
   int32_t reserved[3];
 } prrp_stats;
 
+/* Compute units that the largest strong-RRQR tile of a factorization
+ * (method 0: LU_PRRP, whose tile is the whole panel; method 1: CALU_PRRP with
+ * `tree` and `tile_rows`) occupies with all its workgroups resident, at
+ * blocks_per_cu workgroups per CU (0: the device's occupancy for each kernel
+ * instance, which needs a GPU; > 0: that value, a pure host computation).
+ * Factor calls reject sizes whose figure exceeds the device's CUs.  Returns 0
+ * or -k for an invalid argument k. */
+int prrp_panel_cus(int method, int64_t n, int b, int tree, int64_t tile_rows, int blocks_per_cu,
+                   int64_t* cus);
+
 /* Workspace bytes for prrp_factor / prrp_factor_mixed (method 0) or
  * calu_prrp_factor (method 1, tile_rows as passed there) on an n x n matrix
  * with panel width b.  Host-only; returns 0 or -k for an invalid argument. */
@@ -89,7 +101,11 @@ int prrp_workspace_size(int64_t n, int b, int method, int64_t tile_rows, size_t*
 /* LU_PRRP (Section 2.1, Algorithm "LU_PRRP factorization"): in-place factor
  * of the n x n matrix A (leading dimension lda), panel width b, strong RRQR
  * threshold tau > 1 (Appendix A).  perm: device int64[n] (output).
- * stats: device prrp_stats (output, required). */
+ * stats: device prrp_stats (output, required).  Every workgroup of one
+ * panel's strong RRQR waits on the others, so they must all be resident at
+ * once: an n whose first panel the device cannot hold (prrp_panel_cus above
+ * its compute units; on MI355X beyond about 65536) returns -2 before anything
+ * is enqueued. */
 int prrp_factor(double* A, int64_t n, int64_t lda, int b, double tau, int64_t* perm,
                 prrp_stats* stats, void* workspace, size_t ws_bytes, void* stream);
 
@@ -103,7 +119,9 @@ int prrp_factor_mixed(double* A, int64_t n, int64_t lda, int b, double tau, int6
  * rows (>= b + 1; a last remainder of <= b rows joins the previous tile),
  * reduced by strong RRQR along a binary or flat tree (`tree`, a
  * prrp_tree_kind); then the panel is factored with the winners as pivots and
- * the step continues as in LU_PRRP.  `schur` as in prrp_factor_mixed. */
+ * the step continues as in LU_PRRP.  `schur` as in prrp_factor_mixed.  A
+ * tile (or tree node) whose strong-RRQR workgroups the device cannot hold at
+ * once returns -7 before anything is enqueued. */
 int calu_prrp_factor(double* A, int64_t n, int64_t lda, int b, double tau, int tree,
                      int64_t tile_rows, int64_t* perm, prrp_stats* stats, void* workspace,
                      size_t ws_bytes, void* stream, int schur);
@@ -123,28 +141,40 @@ int prrp_solve(const double* LU, int64_t n, int64_t lda, const int64_t* perm, do
 int prrp_residual(const double* A, int64_t n, int64_t lda, const double* X, const double* B,
                   double* R, int64_t nrhs, int64_t ldx, void* stream);
 
+/* Outcome of a refinement run (the `status` outputs below).  A run that did
+ * not converge still returns 0 (its launches succeeded); the status says why
+ * it stopped:
+ *   PRRP_IR_CONVERGED  the last correction was at most tol max|X|;
+ *   PRRP_IR_STAGNATED  the last correction did not halve (or was NaN); it has
+ *                      been applied, and X is only as accurate as the last
+ *                      ratio says (final_rel);
+ *   PRRP_IR_CAP        max_iter corrections were taken without either. */
+enum { PRRP_IR_CONVERGED = 0, PRRP_IR_STAGNATED = 1, PRRP_IR_CAP = 2 };
+
 /* Iterative refinement of the solution of A X = B (used with the paper's
  * linear-solver experiments): X = solve(B); repeat R = prrp_residual; D =
  * solve(R); X += D, until max|D| <= tol max|X| per right-hand side, the
  * correction stops halving, or max_iter corrections.  This call synchronizes
  * `stream` once per iteration to test convergence.  iters (host, may be
  * NULL) receives the number of corrections; final_rel (host, may be NULL) the
- * last max|D|/max|X|. */
+ * last max|D|/max|X|; status (host, may be NULL) a PRRP_IR_* value. */
 int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const int64_t* perm,
                 const double* B, double* X, int64_t nrhs, int64_t ldx, double tol, int max_iter,
-                int* iters, double* final_rel, void* workspace, size_t ws_bytes, void* stream);
+                int* iters, double* final_rel, int* status, void* workspace, size_t ws_bytes,
+                void* stream);
 
 /* prrp_refine with the whole loop enqueued on `stream` and no host
  * synchronisation: the stopping test runs on the device and the kernels of
  * later iterations return at once once it is met, so the call can be
  * captured in a HIP graph.  At most max_iter (<= 1000) corrections.  iters
  * (device int32, may be NULL) receives the number of corrections, final_rel
- * (device double, may be NULL) the last max|D|/max|X|.  Results are identical
- * to prrp_refine's for the same arguments. */
+ * (device double, may be NULL) the last max|D|/max|X|, status (device int32,
+ * may be NULL) a PRRP_IR_* value.  Results are identical to prrp_refine's for
+ * the same arguments. */
 int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
                       const int64_t* perm, const double* B, double* X, int64_t nrhs, int64_t ldx,
                       double tol, int max_iter, int32_t* iters, double* final_rel,
-                      void* workspace, size_t ws_bytes, void* stream);
+                      int32_t* status, void* workspace, size_t ws_bytes, void* stream);
 
 /* Batched LU_PRRP of `count` independent systems of uneven sizes (the
  * algorithm of Section 2.1 on each).  A plan fixes the problems: A[i] (device,
@@ -179,18 +209,14 @@ int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, co
                            double tol, int max_iter, void* workspace, size_t ws_bytes,
                            void* stream, void** plan);
 int prrp_batch_plan_run(void* plan, void* stream, int use_graph);
-/* Copies the refinement iteration counts and last ratios (count each) to the
- * host with copies on `stream`, and waits for that stream (NULL skips). */
-int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels, void* stream);
+/* Copies the refinement iteration counts, last ratios and PRRP_IR_* status
+ * values (count each; any pointer may be NULL to skip it) to the host with
+ * copies on `stream`, and waits for that stream. */
+int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels, int32_t* status,
+                            void* stream);
 /* Releases the plan's host state (graph, events); the workspace is the
  * caller's.  Work the plan enqueued must have completed. */
 int prrp_batch_plan_destroy(void* plan);
-/* One-shot batched factorization: allocates a workspace, creates, runs and
- * destroys a plan, and waits for the stream (synchronous, allocating). */
-int prrp_factor_batched(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
-                        const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
-                        int schur, void* stream);
-
 /* C = alpha A B + beta C for row-major FP64 matrices (M x K, K x N, M x N),
  * computed by the MFMA kernel of the Schur-complement update (equation
  * "update", Section 2.1).  prec: a prrp_precision; with FP32 / BF16 the

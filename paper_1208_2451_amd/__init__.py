@@ -134,7 +134,8 @@ def residual(A, X, B):
 
 
 def refine(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30, workspace=None):
-    """Iterative refinement; returns (X, iterations, last max|dX|/max|X|)."""
+    """Iterative refinement; returns (X, iterations, last max|dX|/max|X|,
+    status), status one of "converged", "stagnated", "cap"."""
     import ctypes
     from . import _lib
     torch = _torch()
@@ -148,19 +149,21 @@ def refine(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30, workspace=Non
         workspace = _alloc(ws_bytes, A.device)
     it = ctypes.c_int(0)
     rel = ctypes.c_double(0.0)
+    status = ctypes.c_int(0)
     code = _lib.lib().prrp_refine(A.data_ptr(), LU.data_ptr(), n, A.stride(0), perm.data_ptr(),
                                   B2.data_ptr(), X.data_ptr(), nrhs, nrhs, float(tol), int(max_iter),
-                                  ctypes.byref(it), ctypes.byref(rel), workspace.data_ptr(),
-                                  workspace.numel(), _stream_ptr())
+                                  ctypes.byref(it), ctypes.byref(rel), ctypes.byref(status),
+                                  workspace.data_ptr(), workspace.numel(), _stream_ptr())
     _lib.check(code, "prrp_refine")
-    return X.view(B.shape), it.value, rel.value
+    return X.view(B.shape), it.value, rel.value, _lib.IR_STATUS[status.value]
 
 
 def refine_async(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30, workspace=None):
     """Iterative refinement enqueued without host synchronisation.
 
-    Returns (X, iters, rel) where iters (int32) and rel (float64) are
-    one-element device tensors filled when the stream reaches them."""
+    Returns (X, iters, rel, status) where iters (int32), rel (float64) and
+    status (int32, a PRRP_IR_* value) are one-element device tensors filled
+    when the stream reaches them."""
     from . import _lib
     torch = _torch()
     _check_matrix(A)
@@ -173,12 +176,14 @@ def refine_async(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30, workspa
         workspace = _alloc(ws_bytes, A.device)
     it = torch.zeros(1, dtype=torch.int32, device=A.device)
     rel = torch.zeros(1, dtype=torch.float64, device=A.device)
+    status = torch.zeros(1, dtype=torch.int32, device=A.device)
     code = _lib.lib().prrp_refine_async(A.data_ptr(), LU.data_ptr(), n, A.stride(0), perm.data_ptr(),
                                         B2.data_ptr(), X.data_ptr(), nrhs, nrhs, float(tol),
                                         int(max_iter), it.data_ptr(), rel.data_ptr(),
-                                        workspace.data_ptr(), workspace.numel(), _stream_ptr())
+                                        status.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                        _stream_ptr())
     _lib.check(code, "prrp_refine_async")
-    return X.view(B.shape), it, rel
+    return X.view(B.shape), it, rel, status
 
 
 class BatchPlan:
@@ -252,16 +257,27 @@ class BatchPlan:
         w = _lib.STATS_BYTES
         return read_stats(self.stats_raw[i * w:(i + 1) * w])
 
+    def infos(self) -> list:
+        """The numerical status (prrp_stats.info) of every system, one copy
+        of the stats records to the host."""
+        from ._lib import Stats
+        host = self.stats_raw.cpu().numpy().tobytes()
+        w = len(host) // len(self.mats)
+        return [int(Stats.from_buffer_copy(host[i * w:(i + 1) * w]).info)
+                for i in range(len(self.mats))]
+
     def refine_results(self):
-        """(iterations, last ratios) per system, copied to the host."""
+        """(iterations, last ratios, statuses) per system, copied to the host;
+        a status is "converged", "stagnated" or "cap"."""
         import ctypes
         from . import _lib
         count = len(self.mats)
         it = (ctypes.c_int32 * count)()
         rel = (ctypes.c_double * count)()
-        _lib.check(_lib.lib().prrp_batch_plan_results(self._h, it, rel, _stream_ptr()),
+        st = (ctypes.c_int32 * count)()
+        _lib.check(_lib.lib().prrp_batch_plan_results(self._h, it, rel, st, _stream_ptr()),
                    "prrp_batch_plan_results")
-        return list(it), list(rel)
+        return list(it), list(rel), [_lib.IR_STATUS[v] for v in st]
 
     def close(self, synchronize: bool = True):
         """Releases the plan (its workspace is a torch tensor freed with this

@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libprrp.so")
 PRRP_FP64, PRRP_SCHUR_FP32, PRRP_SCHUR_BF16 = 0, 1, 2
 PRRP_TREE_BINARY, PRRP_TREE_FLAT = 0, 1
 PRECISIONS = {"fp64": PRRP_FP64, "fp32": PRRP_SCHUR_FP32, "bf16": PRRP_SCHUR_BF16}
+PRRP_IR_CONVERGED, PRRP_IR_STAGNATED, PRRP_IR_CAP = 0, 1, 2
+IR_STATUS = {PRRP_IR_CONVERGED: "converged", PRRP_IR_STAGNATED: "stagnated", PRRP_IR_CAP: "cap"}
 TREES = {"binary": PRRP_TREE_BINARY, "flat": PRRP_TREE_FLAT}
 
 
@@ -45,17 +47,18 @@ _SIGS = {
     "prrp_solve": (_i32, [_vp, _i64, _i64, _vp, _vp, _i64, _i64, _vp, _sz, _vp]),
     "prrp_residual": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _vp]),
     "prrp_refine": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _dbl, _i32,
-                           ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _sz, _vp]),
+                           ctypes.POINTER(_i32), ctypes.POINTER(_dbl), ctypes.POINTER(_i32),
+                           _vp, _sz, _vp]),
     "prrp_refine_async": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _dbl, _i32,
-                                 _vp, _vp, _vp, _sz, _vp]),
+                                 _vp, _vp, _vp, _vp, _sz, _vp]),
+    "prrp_panel_cus": (_i32, [_i32, _i64, _i32, _i32, _i64, _i32, ctypes.POINTER(_i64)]),
     "prrp_batch_plan_workspace_size": (_i32, [_i64, _vp, _vp, _vp, _i32, ctypes.POINTER(_sz)]),
     "prrp_batch_plan_create": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, _i32,
                                       _vp, _vp, _vp, _vp, _dbl, _i32, _vp, _sz, _vp,
                                       ctypes.POINTER(_vp)]),
     "prrp_batch_plan_run": (_i32, [_vp, _vp, _i32]),
-    "prrp_batch_plan_results": (_i32, [_vp, _vp, _vp, _vp]),
+    "prrp_batch_plan_results": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "prrp_batch_plan_destroy": (_i32, [_vp]),
-    "prrp_factor_batched": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32, _vp]),
     "prrp_gemm": (_i32, [_i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64, _dbl, _vp, _i64, _i32, _vp]),
     "prrp_profile_enable": (_i32, [_i32]),
     "prrp_profile_read": (_i32, [ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),

@@ -98,6 +98,27 @@ int groups_for_rows(int64_t rows, int cap, int target = 64) {
   return (int)std::max<int64_t>(1, (rows + rpw - 1) / rpw);
 }
 
+// Compute units that one strong-RRQR tile of G workgroups (bw columns, rpw
+// rows each) occupies when all of them are resident, or -1 if the occupancy
+// query fails.  Every workgroup of a tile waits on the others, so the tile
+// must fit at once.
+int64_t tile_cus(int G, int bw, int rpw, int bpc_given = 0) {
+  if (bpc_given > 0) return (G + bpc_given - 1) / bpc_given;
+  static std::mutex mu;
+  static std::vector<std::pair<int64_t, int>> cache;   // ((bw << 32) | rpw, blocks)
+  const int64_t key = ((int64_t)bw << 32) | (uint32_t)rpw;
+  int bpc = 0;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& kv : cache) if (kv.first == key) bpc = kv.second;
+    if (bpc == 0) {
+      if (srrqr_blocks_per_cu(bw, rpw, &bpc) != hipSuccess || bpc < 1) return -1;
+      cache.push_back({key, bpc});
+    }
+  }
+  return (G + bpc - 1) / bpc;
+}
+
 struct Layout {
   size_t slots_set_words = 0;     // words per slot set
   size_t off_slots = 0, off_rounds = 0, off_abort = 0, off_sel = 0, off_lists = 0;
@@ -579,6 +600,37 @@ int validate_common(double* A, int64_t n, int64_t lda, int b, double tau, int64_
   return 0;
 }
 
+// The most compute units any tile of any strong-RRQR launch of this
+// factorization needs at once (-1: occupancy query failed).
+int64_t factor_tile_cus(int method, int64_t n, int b, int tree, int64_t tile_rows, int cap,
+                        int rpw_target, int bpc_given = 0) {
+  int64_t need = 0;
+  auto one = [&](int64_t rows, int bw) {
+    const int G = groups_for_rows(rows, cap, rpw_target);
+    const int rpw = (int)((rows + G - 1) / G);
+    const int64_t c = tile_cus(G, bw, rpw, bpc_given);
+    need = (c < 0 || need < 0) ? -1 : std::max(need, c);
+  };
+  for (int64_t k0 = 0; k0 < n && need >= 0; k0 += b) {
+    const int bw = (int)std::min<int64_t>(b, n - k0);
+    const int64_t m = n - k0;
+    if (method == 0) { one(m, bw); continue; }
+    const Tiles t = tile_bounds(m, tile_rows, bw);
+    one(m, bw);                                    // one tile, or the root's QR
+    if (t.start.size() == 1) continue;
+    int maxlen = 0;
+    for (int l : t.len) maxlen = std::max(maxlen, l);
+    if (tree == PRRP_TREE_BINARY) {
+      one(maxlen, bw);
+      one(2 * bw, bw);
+    } else {
+      one(t.len[0], bw);
+      for (size_t i = 1; i < t.len.size(); ++i) one(bw + t.len[i], bw);
+    }
+  }
+  return need;
+}
+
 int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau, int tree,
                int64_t tile_rows, int64_t* perm, prrp_stats* stats, void* workspace,
                size_t ws_bytes, void* stream, int schur, bool lookahead = true,
@@ -592,6 +644,11 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
   c.cap = std::min(256, device_cus());
   c.L = make_layout(n, b, method, tile_rows);
   PRRP_TRY(srrqr_prepare());
+  // every workgroup of a strong-RRQR tile waits on the others: a tile that
+  // the device cannot hold at once is an argument error, found here
+  const int64_t need_cus = factor_tile_cus(method, n, b, tree, tile_rows, c.cap, c.rpw_target);
+  if (need_cus < 0) return herr(hipErrorInvalidValue);
+  if (need_cus > device_cus()) return method == 0 ? -2 : -7;
   hipStream_t caller = c.st;
   // The look-ahead streams and their event ring are shared by the process:
   // one host thread at a time enqueues a factorization on them.
@@ -606,10 +663,10 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
     hipEvent_t e0 = side_event();
     PRRP_TRY(hipEventRecord(e0, caller));
     PRRP_TRY(hipStreamWaitEvent(c.side, e0, 0));
-    // every workgroup of a strong-RRQR launch must be resident at once: one
-    // LU_PRRP panel (at most 64) fits the reserved CUs, a CALU_PRRP
-    // tournament level need not
-    const bool fits = g_side.main_cus == 0 || panel_wg_cap() <= g_side.main_cus;
+    // the panel chain keeps to the reserved CUs when every strong-RRQR tile
+    // of the factorization fits them (a CALU_PRRP tournament level spans
+    // several tiles, which need not be resident together)
+    const bool fits = g_side.main_cus == 0 || need_cus <= g_side.main_cus;
     hipStream_t chain = (method == 0 && fits) ? g_side.main : g_side.main_any;
     PRRP_TRY(hipStreamWaitEvent(chain, e0, 0));
     PRRP_TRY(hipStreamWaitEvent(g_side.s2, e0, 0));
@@ -780,6 +837,26 @@ const char* prrp_status_string(int code) {
   return "singular: exactly zero residual or pivot at this 1-based column";
 }
 
+int prrp_panel_cus(int method, int64_t n, int b, int tree, int64_t tile_rows, int blocks_per_cu,
+                   int64_t* cus) {
+  if (method != 0 && method != 1) return -1;
+  if (n < 1 || n > kMaxN) return -2;
+  if (b < 1 || b > kMaxB || b > n) return -3;
+  if (method == 1 && tree != PRRP_TREE_BINARY && tree != PRRP_TREE_FLAT) return -4;
+  if (method == 1 && tile_rows < b + 1) return -5;
+  if (blocks_per_cu < 0) return -6;
+  if (!cus) return -7;
+  if (blocks_per_cu == 0) {
+    const hipError_t e = srrqr_prepare();
+    if (e != hipSuccess) return herr(e);
+  }
+  const int64_t c = factor_tile_cus(method, n, b, tree, method == 1 ? tile_rows : 0,
+                                    std::min(256, device_cus()), 64, blocks_per_cu);
+  if (c < 0) return herr(hipErrorInvalidValue);
+  *cus = c;
+  return 0;
+}
+
 int prrp_workspace_size(int64_t n, int b, int method, int64_t tile_rows, size_t* bytes) {
   if (n < 1 || n > kMaxN) return -1;
   if (b < 1 || b > kMaxB || b > n) return -2;
@@ -922,7 +999,8 @@ int prrp_residual(const double* A, int64_t n, int64_t lda, const double* X, cons
 
 int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const int64_t* perm,
                 const double* B, double* X, int64_t nrhs, int64_t ldx, double tol, int max_iter,
-                int* iters, double* final_rel, void* workspace, size_t ws_bytes, void* stream) {
+                int* iters, double* final_rel, int* status, void* workspace, size_t ws_bytes,
+                void* stream) {
   if (!A) return -1;
   if (!LU) return -2;
   if (n < 1 || n > kMaxN) return -3;
@@ -949,6 +1027,7 @@ int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const
   double prev = INFINITY;
   int it = 0;
   double rel = INFINITY;
+  int stat = PRRP_IR_CAP;        // the same test as the device-side loop
   for (it = 1; it <= max_iter; ++it) {
     PRRP_TRY(launch_residual(A, n, lda, X, ldx, B, ldx, R, nrhs, nrhs, nullptr, st));
     rc = solve_impl(LU, n, lda, perm, R, nrhs, R, nrhs, nrhs, ws, st);
@@ -962,18 +1041,20 @@ int prrp_refine(const double* A, const double* LU, int64_t n, int64_t lda, const
       const double xm = h[2 * r + 1] > 0.0 ? h[2 * r + 1] : 1.0;
       rel = std::max(rel, h[2 * r] / xm);
     }
-    if (!(rel > tol) || rel > 0.5 * prev) break;
+    if (rel <= tol) { stat = PRRP_IR_CONVERGED; break; }
+    if (!(rel <= 0.5 * prev)) { stat = PRRP_IR_STAGNATED; break; }
     prev = rel;
   }
   if (iters) *iters = std::min(it, max_iter);
-  if (final_rel) *final_rel = rel;
+  if (final_rel) *final_rel = max_iter > 0 ? rel : 0.0;
+  if (status) *status = stat;
   return 0;
 }
 
 int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
                       const int64_t* perm, const double* B, double* X, int64_t nrhs, int64_t ldx,
                       double tol, int max_iter, int32_t* iters, double* final_rel,
-                      void* workspace, size_t ws_bytes, void* stream) {
+                      int32_t* status, void* workspace, size_t ws_bytes, void* stream) {
   if (!A) return -1;
   if (!LU) return -2;
   if (n < 1 || n > kMaxN) return -3;
@@ -987,12 +1068,12 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
   if (max_iter < 0 || max_iter > 1000) return -11;
   size_t need = 0;
   prrp_solve_workspace_size(n, nrhs, &need);
-  if (!workspace) return -14;
-  if (ws_bytes < need) return -15;
+  if (!workspace) return -15;
+  if (ws_bytes < need) return -16;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   SolveWs w(ws, n, nrhs);
-  PRRP_TRY(launch_ir_init(w.ir, w.mx, nrhs, iters, final_rel, st));
+  PRRP_TRY(launch_ir_init(w.ir, w.mx, nrhs, iters, final_rel, status, st));
   int rc = solve_impl(LU, n, lda, perm, B, ldx, X, nrhs, ldx, ws, st);
   if (rc) return rc;
   const uint32_t* done = &w.ir->done;
@@ -1001,7 +1082,7 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
     rc = solve_impl(LU, n, lda, perm, w.r, nrhs, w.r, nrhs, nrhs, ws, st, done);
     if (rc) return rc;
     PRRP_TRY(launch_axpy_maxrel(X, ldx, w.r, nrhs, n, nrhs, w.mx, done, st));
-    PRRP_TRY(launch_ir_check(w.ir, w.mx, nrhs, tol, max_iter, iters, final_rel, st));
+    PRRP_TRY(launch_ir_check(w.ir, w.mx, nrhs, tol, max_iter, iters, final_rel, status, st));
   }
   return 0;
 }
@@ -1065,7 +1146,7 @@ struct BatchPlan {
   size_t need = 0;
   size_t lists_at = 0;
   size_t slots_begin = 0, slots_end = 0;
-  size_t off_abort = 0, off_iters = 0, off_rels = 0;
+  size_t off_abort = 0, off_iters = 0, off_rels = 0, off_status = 0;
   std::vector<char> host;           // work lists (host image, uploaded at creation)
   std::vector<PlanOp> ops;
   std::vector<SrrqrArgs> srrqr_args;
@@ -1107,6 +1188,7 @@ void plan_build(BatchPlan& P) {
   P.off_abort = take(256);
   P.off_iters = take((size_t)count * 4);
   P.off_rels = take((size_t)count * 8);
+  P.off_status = take((size_t)count * 4);
   P.lists_at = align_up(off, 256);
 
   std::vector<char>& host = P.host;
@@ -1301,12 +1383,13 @@ void plan_relocate(BatchPlan& P) {
     IrArgs* irl = reinterpret_cast<IrArgs*>(P.host.data() + P.ir_list_off);
     int32_t* iters = reinterpret_cast<int32_t*>(base + P.off_iters);
     double* rels = reinterpret_cast<double*>(base + P.off_rels);
+    int32_t* stat = reinterpret_cast<int32_t*>(base + P.off_status);
     for (size_t i = 0; i < P.p.size(); ++i) {
       PlanProblem& q = P.p[i];
       q.sws = base + q.off_sws;
       SolveWs w(q.sws, q.n, q.nrhs);
       irl[i] = IrArgs{q.A0, q.n, q.lda, q.A, q.perm, q.B, q.X, q.nrhs, w.t1, w.t2, w.r, w.mx,
-                      w.ticket, w.ir, iters + i, rels + i};
+                      w.ticket, w.ir, iters + i, rels + i, stat + i};
     }
   }
 }
@@ -1449,6 +1532,13 @@ int prrp_batch_plan_create(int64_t count, double* const* A, const int64_t* n, co
   hipError_t e = srrqr_prepare();
   if (e == hipSuccess) e = prepare_batched_kernels();
   if (e != hipSuccess) { plan_free(P); return herr(e); }
+  // each problem's strong-RRQR workgroups wait on each other: a problem
+  // whose panel the device cannot hold at once is an argument error
+  for (const SrrqrArgs& a : P->srrqr_args) {
+    const int64_t c = tile_cus(a.G, a.bw, a.rpw);
+    if (c < 0) { plan_free(P); return herr(hipErrorInvalidValue); }
+    if (c > device_cus()) { plan_free(P); return -3; }
+  }
   P->base = static_cast<char*>(workspace);
   plan_relocate(*P);
   // the host image stays alive in the plan until destruction
@@ -1480,13 +1570,16 @@ int prrp_batch_plan_run(void* plan, void* stream, int use_graph) {
   return herr(hipGraphLaunch(P.exec, st));
 }
 
-int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels, void* stream) {
+int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels, int32_t* status,
+                            void* stream) {
   if (!plan) return -1;
   BatchPlan& P = *static_cast<BatchPlan*>(plan);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t c = P.p.size();
   if (iters) PRRP_TRY(hipMemcpyAsync(iters, P.base + P.off_iters, c * 4, hipMemcpyDeviceToHost, st));
   if (rels) PRRP_TRY(hipMemcpyAsync(rels, P.base + P.off_rels, c * 8, hipMemcpyDeviceToHost, st));
+  if (status)
+    PRRP_TRY(hipMemcpyAsync(status, P.base + P.off_status, c * 4, hipMemcpyDeviceToHost, st));
   PRRP_TRY(hipStreamSynchronize(st));
   return 0;
 }
@@ -1494,25 +1587,6 @@ int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels, void* stre
 int prrp_batch_plan_destroy(void* plan) {
   plan_free(static_cast<BatchPlan*>(plan));
   return 0;
-}
-
-int prrp_factor_batched(int64_t count, double* const* A, const int64_t* n, const int64_t* lda,
-                        const int* b, int64_t* const* perm, prrp_stats* stats, double tau,
-                        int schur, void* stream) {
-  size_t need = 0;
-  int rc = prrp_batch_plan_workspace_size(count, n, b, nullptr, 64, &need);
-  if (rc) return rc;
-  void* ws = nullptr;
-  if (hipMalloc(&ws, need) != hipSuccess) return -1002;
-  void* plan = nullptr;
-  rc = prrp_batch_plan_create(count, A, n, lda, b, perm, stats, tau, schur, 64, nullptr, nullptr,
-                              nullptr, nullptr, 0.0, 0, ws, need, stream, &plan);
-  if (rc == 0) rc = prrp_batch_plan_run(plan, stream, 0);
-  const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
-  if (plan) prrp_batch_plan_destroy(plan);
-  (void)hipFree(ws);
-  if (rc) return rc;
-  return herr(e);
 }
 
 }  // extern "C"

@@ -75,6 +75,9 @@ hipError_t launch_srrqr(const SrrqrArgs& a, hipStream_t stream);
 size_t srrqr_smem_bytes(int bw);
 int srrqr_max_rpw();
 hipError_t srrqr_prepare();   // raise the dynamic LDS limit of every instance
+// Workgroups of the instance for (bw, rows per workgroup) one CU holds at once
+// (after srrqr_prepare).  Every workgroup of a tile must be resident together.
+hipError_t srrqr_blocks_per_cu(int bw, int rpw, int* blocks);
 
 // ----------------------------------------------- diagonal block and moves
 struct GeppArgs {
@@ -211,9 +214,10 @@ struct IrState {
   double prev;
 };
 hipError_t launch_ir_init(IrState* st, double* mx, int64_t nrhs, int32_t* iters_out,
-                          double* rel_out, hipStream_t s);
+                          double* rel_out, int32_t* status_out, hipStream_t s);
 hipError_t launch_ir_check(IrState* st, double* mx, int64_t nrhs, double tol, int max_iter,
-                           int32_t* iters_out, double* rel_out, hipStream_t s);
+                           int32_t* iters_out, double* rel_out, int32_t* status_out,
+                           hipStream_t s);
 
 // One system of a batched refinement (right-hand sides with ld = nrhs; the
 // buffers are the system's solve workspace).
@@ -230,6 +234,7 @@ struct IrArgs {
   IrState* st;
   int32_t* iters_out;
   double* rel_out;
+  int32_t* status_out;        // PRRP_IR_* of the last stopping test
 };
 // The whole refinement loop of prrp_refine_async for every system of a list,
 // one launch per sub-step over all systems.

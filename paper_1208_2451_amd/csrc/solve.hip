@@ -339,7 +339,8 @@ hipError_t launch_axpy_maxrel(double* X, int64_t ldx, const double* D, int64_t l
 // test runs in ir_check_kernel and later iterations' kernels see `done` and
 // return at once.
 __device__ __forceinline__ void ir_init_body(IrState* st, double* mx, int64_t nrhs,
-                                             int32_t* iters_out, double* rel_out) {
+                                             int32_t* iters_out, double* rel_out,
+                                             int32_t* status_out) {
   const int t = threadIdx.x;
   if (t == 0) {
     st->done = 0u;
@@ -347,15 +348,19 @@ __device__ __forceinline__ void ir_init_body(IrState* st, double* mx, int64_t nr
     st->prev = __longlong_as_double(0x7FF0000000000000ll);   // +inf
     if (iters_out) *iters_out = 0;
     if (rel_out) *rel_out = 0.0;
+    if (status_out) *status_out = PRRP_IR_CAP;   // no correction taken yet
   }
   for (int64_t i = t; i < 2 * nrhs; i += blockDim.x) mx[i] = 0.0;
 }
 
 // Same stopping test as the host-driven loop: stop when the correction is at
 // most tol times the solution (per right-hand side, worst case), or when it
-// no longer halves, or after max_iter corrections.
+// no longer halves, or after max_iter corrections.  The status says which
+// (PRRP_IR_CONVERGED, PRRP_IR_STAGNATED, PRRP_IR_CAP); a NaN correction
+// counts as stagnation.
 __device__ __forceinline__ void ir_check_body(IrState* st, double* mx, int64_t nrhs, double tol,
-                                              int max_iter, int32_t* iters_out, double* rel_out) {
+                                              int max_iter, int32_t* iters_out, double* rel_out,
+                                              int32_t* status_out) {
   if (threadIdx.x != 0 || st->done) return;
   double rel = 0.0;
   for (int64_t r = 0; r < nrhs; ++r) {
@@ -366,31 +371,37 @@ __device__ __forceinline__ void ir_check_body(IrState* st, double* mx, int64_t n
   }
   const unsigned it = st->iter + 1u;
   st->iter = it;
-  if (!(rel > tol) || rel > 0.5 * st->prev || (int)it >= max_iter) st->done = 1u;
+  int32_t status = PRRP_IR_CAP;
+  if (rel <= tol) status = PRRP_IR_CONVERGED;
+  else if (!(rel <= 0.5 * st->prev)) status = PRRP_IR_STAGNATED;
+  if (status != PRRP_IR_CAP || (int)it >= max_iter) st->done = 1u;
   st->prev = rel;
   if (iters_out) *iters_out = (int32_t)it;
   if (rel_out) *rel_out = rel;
+  if (status_out) *status_out = status;
 }
 
 __global__ void ir_init_kernel(IrState* st, double* mx, int64_t nrhs, int32_t* iters_out,
-                               double* rel_out) {
-  ir_init_body(st, mx, nrhs, iters_out, rel_out);
+                               double* rel_out, int32_t* status_out) {
+  ir_init_body(st, mx, nrhs, iters_out, rel_out, status_out);
 }
 __global__ void ir_check_kernel(IrState* st, double* mx, int64_t nrhs, double tol, int max_iter,
-                                int32_t* iters_out, double* rel_out) {
-  ir_check_body(st, mx, nrhs, tol, max_iter, iters_out, rel_out);
+                                int32_t* iters_out, double* rel_out, int32_t* status_out) {
+  ir_check_body(st, mx, nrhs, tol, max_iter, iters_out, rel_out, status_out);
 }
 
 hipError_t launch_ir_init(IrState* st, double* mx, int64_t nrhs, int32_t* iters_out,
-                          double* rel_out, hipStream_t s) {
-  hipLaunchKernelGGL(ir_init_kernel, dim3(1), dim3(64), 0, s, st, mx, nrhs, iters_out, rel_out);
+                          double* rel_out, int32_t* status_out, hipStream_t s) {
+  hipLaunchKernelGGL(ir_init_kernel, dim3(1), dim3(64), 0, s, st, mx, nrhs, iters_out, rel_out,
+                     status_out);
   return hipGetLastError();
 }
 
 hipError_t launch_ir_check(IrState* st, double* mx, int64_t nrhs, double tol, int max_iter,
-                           int32_t* iters_out, double* rel_out, hipStream_t s) {
+                           int32_t* iters_out, double* rel_out, int32_t* status_out,
+                           hipStream_t s) {
   hipLaunchKernelGGL(ir_check_kernel, dim3(1), dim3(64), 0, s, st, mx, nrhs, tol, max_iter,
-                     iters_out, rel_out);
+                     iters_out, rel_out, status_out);
   return hipGetLastError();
 }
 
@@ -402,7 +413,7 @@ hipError_t launch_ir_check(IrState* st, double* mx, int64_t nrhs, double tol, in
 // the first solve of B into X; phase 1: the correction solve of R in place.
 __global__ void ir_init_batched_kernel(const IrArgs* list) {
   const IrArgs a = list[blockIdx.x];
-  ir_init_body(a.st, a.mx, a.nrhs, a.iters_out, a.rel_out);
+  ir_init_body(a.st, a.mx, a.nrhs, a.iters_out, a.rel_out, a.status_out);
 }
 
 __global__ void gather_batched_kernel(const IrArgs* list, int phase) {
@@ -438,7 +449,7 @@ __global__ __launch_bounds__(256) void axpy_batched_kernel(const IrArgs* list) {
 
 __global__ void ir_check_batched_kernel(const IrArgs* list, double tol, int max_iter) {
   const IrArgs a = list[blockIdx.x];
-  ir_check_body(a.st, a.mx, a.nrhs, tol, max_iter, a.iters_out, a.rel_out);
+  ir_check_body(a.st, a.mx, a.nrhs, tol, max_iter, a.iters_out, a.rel_out, a.status_out);
 }
 
 hipError_t launch_refine_batched(const IrArgs* list, int count, int64_t max_n, int64_t max_nrhs,

@@ -504,7 +504,8 @@ void srrqr_kernel(SrrqrArgs a) {
           }
           if (tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
           uint64_t kv = 0;
-          if (tid < G) kv = poll_word(post_r + (size_t)tid * kPostW, a.abort_flag, &bad);
+          for (int m = tid; m < G; m += kThreads)
+            kv = umax(kv, poll_word(post_r + (size_t)m * kPostW, a.abort_flag, &bad));
           kv = wave_max_u64(kv);
           if (lane == 0) S.red[4 + wave] = kv;
           if (bad) S.flags[0] = 1;
@@ -741,6 +742,25 @@ hipError_t launch_srrqr(const SrrqrArgs& a, hipStream_t stream) {
 }
 
 int srrqr_max_rpw() { return kRowGroups * 4; }
+
+#define PRRP_SRRQR_OCC(C, R)                                                                \
+  if (cpt == C && rpt == R)                                                                 \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, srrqr_kernel<C, R>, kThreads, \
+                                                        smem);
+
+// Workgroups of one instance that a compute unit holds at once.
+hipError_t srrqr_blocks_per_cu(int bw, int rpw, int* blocks) {
+  int cpt = (bw + 7) / 8;
+  cpt = cpt <= 2 ? (cpt <= 1 ? 1 : 2) : (cpt <= 4 ? 4 : (cpt <= 8 ? 8 : 16));
+  const int rpt = (rpw + kRowGroups - 1) / kRowGroups;
+  const size_t smem = srrqr_smem_bytes(bw);
+  PRRP_SRRQR_OCC(1, 1) PRRP_SRRQR_OCC(1, 2) PRRP_SRRQR_OCC(1, 3) PRRP_SRRQR_OCC(1, 4)
+  PRRP_SRRQR_OCC(2, 1) PRRP_SRRQR_OCC(2, 2) PRRP_SRRQR_OCC(2, 3) PRRP_SRRQR_OCC(2, 4)
+  PRRP_SRRQR_OCC(4, 1) PRRP_SRRQR_OCC(4, 2) PRRP_SRRQR_OCC(4, 3) PRRP_SRRQR_OCC(4, 4)
+  PRRP_SRRQR_OCC(8, 1) PRRP_SRRQR_OCC(8, 2) PRRP_SRRQR_OCC(8, 3) PRRP_SRRQR_OCC(8, 4)
+  PRRP_SRRQR_OCC(16, 1) PRRP_SRRQR_OCC(16, 2) PRRP_SRRQR_OCC(16, 3) PRRP_SRRQR_OCC(16, 4)
+  return hipErrorInvalidValue;
+}
 
 #define PRRP_SRRQR_ATTR(C, R)                                                               \
   e = hipFuncSetAttribute((const void*)srrqr_kernel<C, R>,                                  \

@@ -34,6 +34,8 @@ class Request:
     B: object = None          # device float64 n x nrhs
     X: object = None          # solution, set on completion
     iters: int = -1
+    status: str = ""          # refinement outcome: converged / stagnated / cap
+    info: int = 0             # the factorization's numerical status (0: ok)
     t_admit: float = -1.0
     t_done: float = -1.0
 
@@ -140,11 +142,14 @@ class Server:
                 if bt is not None and bt.event.query():
                     t = time.perf_counter() - t0
                     with torch.cuda.stream(self.streams[k]):
-                        its, _ = bt.plan.refine_results()
-                    for r, x, it in zip(bt.reqs, bt.plan.solutions, its):
+                        its, _, sts = bt.plan.refine_results()
+                        infos = bt.plan.infos()
+                    for r, x, it, stt, inf in zip(bt.reqs, bt.plan.solutions, its, sts, infos):
                         r.t_done = t
                         r.X = x
                         r.iters = it
+                        r.status = stt
+                        r.info = inf
                     bt.plan.close(synchronize=False)
                     used -= bt.bytes
                     done += len(bt.reqs)
@@ -195,6 +200,10 @@ class Server:
             "tflops": flops / span / 1e12,
             "span_s": span,
             "max_iters": int(max(r.iters for r in reqs)),
+            # requests whose refinement stopped short of tol, or whose
+            # factorization reported a numerical status: served, but flagged
+            "not_converged": int(sum(r.status != "converged" for r in reqs)),
+            "factor_info_nonzero": int(sum(r.info != 0 for r in reqs)),
         }
 
 
@@ -207,7 +216,7 @@ def solve_alone(req, precision="fp32", tau=2.0, tol=1e-14, max_iter=10, rows_per
                      originals=[req.A], rhs=[req.B], tol=tol, max_iter=max_iter)
     plan.run()
     torch.cuda.synchronize()
-    its, _ = plan.refine_results()
+    its, _, _ = plan.refine_results()
     x = plan.solutions[0].clone()
     plan.close()
     return x, its[0]

@@ -92,17 +92,66 @@ def test_solve_and_gemm_argument_errors(L):
 def test_refine_argument_errors(L):
     it = ctypes.c_int(0)
     rel = ctypes.c_double(0)
-    assert L.prrp_refine(1, 1, 8, 8, 1, 1, 1, 1, 1, -1.0, 5, ctypes.byref(it), ctypes.byref(rel),
-                         1, 1 << 30, None) == -10
+    st = ctypes.c_int(0)
+    f = L.prrp_refine
+    assert f(1, 1, 8, 8, 1, 1, 1, 1, 1, -1.0, 5, ctypes.byref(it), ctypes.byref(rel),
+             ctypes.byref(st), 1, 1 << 30, None) == -10
+    assert f(1, 1, 8, 8, 1, 1, 1, 1, 1, 1e-14, 5, None, None, None, None, 1 << 30, None) == -15
+    assert f(1, 1, 8, 8, 1, 1, 1, 1, 1, 1e-14, 5, None, None, None, 1, 16, None) == -16
 
 
 def test_refine_async_argument_errors(L):
-    assert L.prrp_refine_async(1, 1, 8, 8, 1, 1, 1, 1, 1, -1.0, 5, None, None, 1, 1 << 30,
-                               None) == -10
-    assert L.prrp_refine_async(1, 1, 8, 8, 1, 1, 1, 1, 1, 1e-14, 5000, None, None, 1, 1 << 30,
-                               None) == -11
-    assert L.prrp_refine_async(1, 1, 8, 8, 1, 1, 1, 1, 1, 1e-14, 5, None, None, 1, 16,
-                               None) == -15
+    f = L.prrp_refine_async
+    assert f(1, 1, 8, 8, 1, 1, 1, 1, 1, -1.0, 5, None, None, None, 1, 1 << 30, None) == -10
+    assert f(1, 1, 8, 8, 1, 1, 1, 1, 1, 1e-14, 5000, None, None, None, 1, 1 << 30, None) == -11
+    assert f(1, 1, 8, 8, 1, 1, 1, 1, 1, 1e-14, 5, None, None, None, None, 1 << 30, None) == -15
+    assert f(1, 1, 8, 8, 1, 1, 1, 1, 1, 1e-14, 5, None, None, None, 1, 16, None) == -16
+
+
+def test_refine_status_codes_match_the_binding(L):
+    # the header's PRRP_IR_* values, as the binding and the server read them
+    with open(os.path.join(ROOT, "include", "prrp.h")) as fh:
+        text = fh.read()
+    m = re.search(r"enum\s*\{\s*PRRP_IR_CONVERGED\s*=\s*(\d+),\s*PRRP_IR_STAGNATED\s*=\s*(\d+),"
+                  r"\s*PRRP_IR_CAP\s*=\s*(\d+)\s*\}", text)
+    assert m, "PRRP_IR_* enum not found"
+    assert tuple(int(v) for v in m.groups()) == (_lib.PRRP_IR_CONVERGED, _lib.PRRP_IR_STAGNATED,
+                                                  _lib.PRRP_IR_CAP)
+    assert sorted(_lib.IR_STATUS) == [0, 1, 2]
+
+
+def test_no_allocating_batched_factor(L):
+    # a batch runs through a plan on the caller's workspace; the one-shot
+    # entry point that allocated and synchronised is gone
+    assert not hasattr(L, "prrp_factor_batched")
+
+
+def _panel_cus(L, method, n, b, tree=0, tile_rows=0, bpc=2):
+    out = ctypes.c_int64(-1)
+    rc = L.prrp_panel_cus(method, n, b, tree, tile_rows, bpc, ctypes.byref(out))
+    return rc, out.value
+
+
+def test_panel_residency_requirement(L):
+    # LU_PRRP: one panel of n rows over workgroups of at most 128 rows, at
+    # least ceil(n / 64) of them up to 64; all resident at once
+    assert _panel_cus(L, 0, 8192, 128) == (0, 32)            # 64 workgroups, 2 per CU
+    assert _panel_cus(L, 0, 8192, 128, bpc=1) == (0, 64)
+    assert _panel_cus(L, 0, 16384, 128) == (0, 64)           # 128 workgroups of 128 rows
+    assert _panel_cus(L, 0, 65536, 128) == (0, 256)          # exactly the MI355X's CUs
+    rc, cus = _panel_cus(L, 0, 70000, 128)
+    assert rc == 0 and cus > 256                            # rejected by the factor call
+    # CALU_PRRP: the tiles are small, but the root factors the whole panel
+    assert _panel_cus(L, 1, 16384, 128, 0, 512)[0] == 0
+    assert _panel_cus(L, 1, 16384, 128, 0, 512)[1] <= 64
+    # argument errors
+    assert _panel_cus(L, 2, 64, 8)[0] == -1
+    assert _panel_cus(L, 0, 0, 8)[0] == -2
+    assert _panel_cus(L, 0, 64, 129)[0] == -3
+    assert _panel_cus(L, 1, 64, 8, 5, 32)[0] == -4
+    assert _panel_cus(L, 1, 64, 8, 0, 8)[0] == -5
+    assert _panel_cus(L, 0, 64, 8, bpc=-1)[0] == -6
+    assert L.prrp_panel_cus(0, 64, 8, 0, 0, 2, None) == -7
 
 
 def test_batch_plan_argument_errors(L):

@@ -142,8 +142,8 @@ def test_refine_async_equals_refine():
     A = A0.clone()
     r = prrp.factor(A, 32, 2.0, precision="fp32")
     B = torch.from_numpy(B_np).cuda()
-    X1, it1, rel1 = prrp.refine(A0, A, r.perm, B, tol=1e-14, max_iter=25)
-    X2, it2, rel2 = prrp.refine_async(A0, A, r.perm, B, tol=1e-14, max_iter=25)
+    X1, it1, rel1, st1 = prrp.refine(A0, A, r.perm, B, tol=1e-14, max_iter=25)
+    X2, it2, rel2, st2 = prrp.refine_async(A0, A, r.perm, B, tol=1e-14, max_iter=25)
     torch.cuda.synchronize()
     assert int(it2.item()) == it1
     assert float(rel2.item()) == rel1
@@ -164,11 +164,11 @@ def test_batch_with_refinement():
                           rhs=B, tol=1e-14, max_iter=20)
     plan.run(graph=True)
     torch.cuda.synchronize()
-    its, rels = plan.refine_results()
+    its, rels, sts = plan.refine_results()
     for i, n in enumerate(sizes):
         Aw = orig[i].clone()
         r = prrp.factor(Aw, _panel(n), 2.0, precision="fp32")
-        X, it, rel = prrp.refine(orig[i], Aw, r.perm, B[i], tol=1e-14, max_iter=20)
+        X, it, rel, status = prrp.refine(orig[i], Aw, r.perm, B[i], tol=1e-14, max_iter=20)
         torch.cuda.synchronize()
         assert its[i] == it
         assert torch.equal(plan.solutions[i].view(X.shape), X)

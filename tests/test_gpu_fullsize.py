@@ -120,7 +120,7 @@ def test_mixed_fp32_n8192_refined_to_1e12(kappa8192, nrhs):
     Af = A0.clone()
     r = prrp.factor(Af, 128, 2.0, precision="fp32")
     Bt = torch.from_numpy(np.ascontiguousarray(B[:, :nrhs])).cuda()
-    X, it, rel = prrp.refine(A0, Af, r.perm, Bt, tol=1e-14, max_iter=30)
+    X, it, rel, status = prrp.refine(A0, Af, r.perm, Bt, tol=1e-14, max_iter=30)
     torch.cuda.synchronize()
     assert r.stats()["info"] == 0
     Xh = X.cpu().numpy().reshape(A.shape[0], nrhs)

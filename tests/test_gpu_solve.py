@@ -70,7 +70,7 @@ def test_refine_kappa_1e6_to_1e12(precision):
     x_ref = _x_ref(A, B[:, 0])
     announce("refine", precision, "n=%d" % n)
     _, _, st, At, r = gpu_factor(A, 64, precision=precision)
-    X, it, rel = prrp.refine(torch.from_numpy(A).cuda(), At, r.perm, torch.from_numpy(B).cuda(),
+    X, it, rel, status = prrp.refine(torch.from_numpy(A).cuda(), At, r.perm, torch.from_numpy(B).cuda(),
                              tol=1e-14, max_iter=40)
     torch.cuda.synchronize()
     err = np.abs(X.cpu().numpy()[:, 0] - x_ref).max() / np.abs(x_ref).max()
@@ -85,7 +85,7 @@ def test_refine_multiple_rhs():
     B = inputs.rhs(n, 8, nrhs)
     announce("refine 16 rhs n=%d" % n)
     _, _, st, At, r = gpu_factor(A, 64)
-    X, it, rel = prrp.refine(torch.from_numpy(A).cuda(), At, r.perm, torch.from_numpy(B).cuda(),
+    X, it, rel, status = prrp.refine(torch.from_numpy(A).cuda(), At, r.perm, torch.from_numpy(B).cuda(),
                              tol=1e-14, max_iter=20)
     torch.cuda.synchronize()
     Xh = X.cpu().numpy()
