@@ -68,14 +68,15 @@ def measured_traffic(kernel_source: str, summary: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def reference_solution(A, b, iters: int = 10):
+def reference_solution(A, b, iters: int = 10, lu_piv=None):
     """Accuracy reference, independent of the library: LAPACK getrf, then
     refinement whose residuals b - A x are accumulated in the host's extended
     precision (x86 long double, 64-bit significand) in row blocks.  Its own
     forward error is a few 1e-14 at kappa = 1e6, far inside the 1e-12 target."""
     import numpy as np
     import scipy.linalg as sla
-    lu_piv = sla.lu_factor(A)
+    if lu_piv is None:
+        lu_piv = sla.lu_factor(A)
     x = sla.lu_solve(lu_piv, b)
     for _ in range(iters):
         xl = x.astype(np.longdouble)
@@ -116,12 +117,12 @@ def cpu_baseline(A_host, b, tau, panels):
             "seconds": dt}
 
 
-def serving_bench(nreq: int, seed: int):
+def serving_bench(nreq: int, seed: int, rates=(0.3, 0.5, 0.7, 1.0)):
     """Continuous-batching solve server: n uniform in {64, 96, ..., 2048},
     b = min(32, n/4), N(0,1) systems with 1-8 right-hand sides, FP32 Schur
     update and FP64 refinement.  The autotuner picks the launch shapes, a
-    saturated run gives the capacity, and the Poisson run arrives at 0.7 of
-    it."""
+    saturated run gives the capacity, and Poisson runs of `nreq` requests
+    arrive at each fraction of it in `rates` (p50 / p99 per rate)."""
     import torch
     from paper_1208_2451_amd import autotune, serving
     t0 = time.perf_counter()
@@ -133,25 +134,112 @@ def serving_bench(nreq: int, seed: int):
                          rows_per_wg=rpw)
     warm = serving.materialize(serving.make_requests(24, seed + 5, 1e9), "cuda")
     srv.serve(warm, realtime=False)
-    sat_reqs = serving.materialize(serving.make_requests(max(48, nreq // 2), seed + 1, 1e9), "cuda")
+    del warm
+    sat_reqs = serving.materialize(serving.make_requests(max(48, nreq // 4), seed + 1, 1e9), "cuda")
     sat = srv.serve(sat_reqs, realtime=False)
+    del sat_reqs
     log("serving saturated", json.dumps(sat))
-    rate = 0.7 * sat["solves_per_s"]
-    reqs = serving.materialize(serving.make_requests(nreq, seed + 2, rate), "cuda")
-    run = srv.serve(reqs, realtime=True)
-    torch.cuda.synchronize()
+    sweep = []
     same = True
-    for r in reqs[:: max(1, len(reqs) // 8)]:
-        x, _ = serving.solve_alone(r, precision="fp32", max_iter=10, rows_per_wg=rpw(r.n))
-        same = same and bool(torch.equal(x, r.X))
-    run.update({"rate_per_s": rate, "saturated_solves_per_s": sat["solves_per_s"],
-                "saturated_tflops": sat["tflops"], "mix_equals_alone_sampled": same,
-                "max_batch": tuning["max_batch"], "rows_per_wg": tuning["rows_per_wg"],
-                "kind": "Poisson arrivals at 0.7 x saturated capacity; n uniform in {64..2048} "
-                        "step 32, b = min(32, n/4), 1-8 rhs, FP32 Schur + FP64 refinement to "
-                        "1e-14; latency = completion - arrival"})
-    del reqs, sat_reqs, warm
-    return run
+    for k, frac in enumerate(rates):
+        rate = frac * sat["solves_per_s"]
+        reqs = serving.materialize(serving.make_requests(nreq, seed + 2 + k, rate), "cuda")
+        run = srv.serve(reqs, realtime=True)
+        torch.cuda.synchronize()
+        if frac == 0.7:
+            for r in reqs[:: max(1, len(reqs) // 8)]:
+                x, _ = serving.solve_alone(r, precision="fp32", max_iter=10, rows_per_wg=rpw(r.n))
+                same = same and bool(torch.equal(x, r.X))
+        run.update({"load": frac, "rate_per_s": rate})
+        log("serving load %.1f" % frac, json.dumps(run))
+        sweep.append(run)
+        del reqs
+        torch.cuda.empty_cache()
+    head = next(r for r in sweep if r["load"] == 0.7) if 0.7 in rates else sweep[-1]
+    out = dict(head)
+    out.update({"saturated_solves_per_s": sat["solves_per_s"], "saturated_tflops": sat["tflops"],
+                "mix_equals_alone_sampled": same, "max_batch": tuning["max_batch"],
+                "rows_per_wg": tuning["rows_per_wg"],
+                "sweep": [{k: r[k] for k in ("load", "rate_per_s", "requests", "solves_per_s",
+                                             "p50_ms", "p99_ms", "not_converged",
+                                             "factor_info_nonzero")} for r in sweep],
+                "kind": "Poisson arrivals at %s x saturated capacity, %d requests each; n uniform "
+                        "in {64..2048} step 32, b = min(32, n/4), 1-8 rhs, FP32 Schur + FP64 "
+                        "refinement to 1e-14; latency = completion - arrival; headline fields at "
+                        "0.7" % (list(rates), nreq)})
+    return out
+
+
+def hpl_metrics(A, x, b):
+    """HPL1, HPL2, HPL3 of the experiments' section (eps = 2^-53), for the
+    record (host NumPy on the solution the device returned)."""
+    import numpy as np
+    eps = 2.0 ** -53
+    n = A.shape[0]
+    r = float(np.abs(A @ x - b).max())
+    a1 = float(np.abs(A).sum(axis=0).max())
+    ainf = float(np.abs(A).sum(axis=1).max())
+    return {"HPL1": r / (eps * a1 * n), "HPL2": r / (eps * a1 * float(np.abs(x).sum())),
+            "HPL3": r / (eps * ainf * float(np.abs(x).max()) * n)}
+
+
+def calu_bench(n: int, b: int, tile_rows: int, tau: float, seed: int, steps: int, warmup: int):
+    """CALU_PRRP, binary tournament over 512-row tiles, on an N(0,1) matrix:
+    factor time and TFLOP/s (2n^3/3), and the per-phase device times."""
+    import torch
+    import paper_1208_2451_amd as prrp
+    from paper_1208_2451_amd import _lib
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    A0 = torch.randn(n, n, generator=g, dtype=torch.float64, device=dev)
+    A = torch.empty_like(A0)
+    ws = torch.empty(_lib.workspace_size(n, b, 1, tile_rows), dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        A.copy_(A0)
+        prrp.calu_factor(A, b, tau, tree="binary", tile_rows=tile_rows, workspace=ws)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        A.copy_(A0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = prrp.calu_factor(A, b, tau, tree="binary", tile_rows=tile_rows, workspace=ws)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    st = r.stats()
+    _lib.profile_enable(True)
+    A.copy_(A0)
+    prrp.calu_factor(A, b, tau, tree="binary", tile_rows=tile_rows, workspace=ws)
+    torch.cuda.synchronize()
+    phases = _lib.profile_read()
+    _lib.profile_enable(False)
+    ms = 1e3 * sum(times) / len(times)
+    nominal = 2.0 * n ** 3 / 3.0
+    ph = {k: v[0] for k, v in phases.items()}
+    out = {"workload": "CALU_PRRP factor, n=%d, b=%d, tau=%g, binary tree over %d-row tiles, "
+                       "N(0,1) matrix" % (n, b, tau, tile_rows),
+           "ms_per_factor": ms, "tflops": nominal / (ms * 1e-3) / 1e12, "steps": steps,
+           "g_W": st["g_W"], "tree_height": st["tree_height"], "info": st["info"],
+           "max_block_L": st["max_block_L"], "swaps": st["swaps"],
+           "phase_ms_per_factor": ph,
+           "phase_launches_per_factor": {k: v[1] for k, v in phases.items()}}
+    # the dominant kernel: the tournament (latency bound) or the Schur GEMM
+    dom = max(("srrqr", "schur"), key=lambda k: ph[k])
+    if dom == "schur":
+        fl = schur_flops(n, b)
+        ach = fl / (ph["schur"] * 1e-3) / 1e12
+        out["roofline"] = {"kernel": "schur_gemm (gemm_kernel<double>)", "bound": "mfma",
+                           "achieved": ach, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                           "frac": ach / PEAK_TFLOPS["fp64"], "traffic": None}
+    else:
+        out["roofline"] = {"kernel": "srrqr_kernel (tournament nodes and leaves)", "bound": "alu",
+                           "ms_per_factor": ph["srrqr"],
+                           "note": "latency bound: (tree height + 1) x b dependent pivot steps "
+                                   "per panel"}
+    del A, A0, ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -163,14 +251,20 @@ def main():
     ap.add_argument("--b", type=int, default=128)
     ap.add_argument("--tau", type=float, default=2.0)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precisions", default="fp64,fp32,bf16")
+    ap.add_argument("--precisions", default="fp64,fp32,fp32-gmres,bf16",
+                    help="variants: Schur precision (fp64, fp32, bf16), optionally -gmres for "
+                         "GMRES-based refinement")
     ap.add_argument("--tol", type=float, default=1e-13)
     ap.add_argument("--cpu-panels", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--solves", type=int, default=200)
-    ap.add_argument("--serving-requests", type=int, default=240,
-                    help="requests of the Poisson serving run (0 skips serving)")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests of each Poisson serving run (0 skips serving)")
+    ap.add_argument("--no-rhs16", dest="rhs16", action="store_false",
+                    help="skip the 16 right-hand-side runs")
+    ap.add_argument("--calu-n", type=int, default=16384,
+                    help="order of the CALU_PRRP run (0 skips it)")
     ap.add_argument("--host-matrix", action="store_true",
                     help="build the kappa matrix with NumPy on the host (same recipe) and copy it "
                          "in, instead of building it with device QR")
@@ -208,38 +302,68 @@ def main():
         log("copy calibration: %d bytes read, %d bytes written" % (8 * n * n, 8 * n * n))
 
     x_ref = None
+    A_host = A0.cpu().numpy()
+    B16 = torch.from_numpy(inputs.rhs(n, args.seed, 16)).to(dev)
     if not args.no_accuracy:
-        log("reference solution: LAPACK getrf + refinement with extended-precision residuals")
-        x_ref = reference_solution(A0.cpu().numpy(), B.cpu().numpy()[:, 0])
+        import scipy.linalg as sla
+        log("reference solutions: LAPACK getrf + refinement with extended-precision residuals")
+        lu_piv = sla.lu_factor(A_host)
+        x_ref = reference_solution(A_host, B.cpu().numpy()[:, 0], lu_piv=lu_piv)
+        B16h = B16.cpu().numpy()
+        x_ref16 = {c: reference_solution(A_host, B16h[:, c], lu_piv=lu_piv) for c in (0, 15)}
+        del lu_piv
 
     nominal = 2.0 * n ** 3 / 3.0
     variants = {}
-    for prec in [p.strip() for p in args.precisions.split(",") if p.strip()]:
-        log("precision", prec)
+    perm64 = None
+    gws = None
+    for variant in [p.strip() for p in args.precisions.split(",") if p.strip()]:
+        # "<schur precision>" refines with one triangular solve per
+        # correction; "<schur precision>-gmres" with GMRES-based refinement
+        prec, _, how = variant.partition("-")
+        gmres = how == "gmres"
+        log("variant", variant)
 
-        def step():
+        def step(rhs=B):
             A.copy_(A0)
             r = prrp.factor(A, b, tau, precision=prec, workspace=ws)
-            X, it, rel, status = prrp.refine(A0, A, r.perm, B, tol=args.tol, max_iter=30,
-                                             workspace=sws)
-            return r, X, it, rel, status
+            if gmres:
+                x, outer, inner, w0, w1, rel, status = prrp.refine_gmres(
+                    A0, A, r.perm, rhs[:, 0], tol=args.tol, gmres_tol=1e-8, max_inner=60,
+                    max_outer=10, workspace=gws)
+                return r, x.view(n, 1), outer, inner, rel, status
+            X, it, rel, status = prrp.refine(A0, A, r.perm, rhs, tol=args.tol, max_iter=30,
+                                             workspace=sws if rhs is B else None)
+            return r, X, it, 0, rel, status
 
+        if gmres and gws is None:
+            import ctypes
+            need = ctypes.c_size_t(0)
+            _lib.check(_lib.lib().prrp_gmres_workspace_size(n, 60, ctypes.byref(need)), "gmres ws")
+            gws = torch.empty(need.value, dtype=torch.uint8, device=dev)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        times, iters, rels = [], [], []
+        times, iters, inners, rels = [], [], [], []
         t_all = time.perf_counter()
         for _ in range(args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r, X, it, rel, status = step()
+            r, X, it, inner, rel, status = step()
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             iters.append(it)
+            inners.append(inner)
             rels.append(rel)
         wall = time.perf_counter() - t_all
         ms = 1e3 * wall / args.steps
         st = r.stats()
+        perm = r.perm.cpu().numpy()
+        if prec == "fp64" and perm64 is None:
+            perm64 = perm
+        # the factors of the last step are in A: the unrefined solution
+        X0 = prrp.solve(A, r.perm, B, workspace=sws)
+        torch.cuda.synchronize()
         # factor-only time and per-phase device times (separate profiled steps)
         _lib.profile_enable(True)
         for _ in range(max(1, min(2, args.steps))):
@@ -254,25 +378,53 @@ def main():
         prrp.factor(A, b, tau, precision=prec, workspace=ws)
         torch.cuda.synchronize()
         factor_ms = 1e3 * (time.perf_counter() - tf0)
-        err = None
+        err = err0 = hpl = None
         if x_ref is not None:
             xg = X.cpu().numpy()[:, 0]
             err = float(np.abs(xg - x_ref).max() / np.abs(x_ref).max())
-        variants[prec] = {
+            err0 = float(np.abs(X0.cpu().numpy()[:, 0] - x_ref).max() / np.abs(x_ref).max())
+            hpl = hpl_metrics(A_host, xg, B.cpu().numpy()[:, 0])
+        variants[variant] = {
             "ms_per_step": ms, "tflops_to_solution": nominal / (ms * 1e-3) / 1e12,
             "factor_ms": factor_ms, "tflops_factor": nominal / (factor_ms * 1e-3) / 1e12,
-            "ir_iterations": iters[-1], "last_correction": rels[-1], "forward_error": err,
-            "meets_1e-12": (err is not None and err <= 1e-12),
+            "refinement": "gmres" if gmres else "one solve per correction",
+            "ir_iterations": iters[-1], "gmres_steps": inners[-1] if gmres else None,
+            "last_correction": rels[-1], "ir_status": status,
+            "forward_error": err, "forward_error_unrefined": err0,
+            "meets_1e-12": (err is not None and err <= 1e-12), "hpl": hpl,
+            "pivots_equal_fp64_fraction": (float(np.mean(perm == perm64))
+                                           if perm64 is not None else None),
             "g_W": st["g_W"], "max_block_L": st["max_block_L"], "swaps": st["swaps"], "info": st["info"],
             "phase_ms_per_factor": {k: v[0] / nprof for k, v in phases.items()},
             "phase_launches_per_factor": {k: v[1] // nprof for k, v in phases.items()},
         }
-        log(prec, json.dumps(variants[prec]))
+        # 16 right-hand sides (the workload's second configuration)
+        if not gmres and args.rhs16:
+            for _ in range(max(1, args.warmup)):
+                step(B16)
+            torch.cuda.synchronize()
+            t16 = []
+            for _ in range(args.steps):
+                t0 = time.perf_counter()
+                r16, X16, it16, _, rel16, st16 = step(B16)
+                torch.cuda.synchronize()
+                t16.append(time.perf_counter() - t0)
+            e16 = None
+            if x_ref is not None:
+                Xh = X16.cpu().numpy()
+                e16 = max(float(np.abs(Xh[:, c] - xr).max() / np.abs(xr).max())
+                          for c, xr in x_ref16.items())
+            variants[variant]["rhs16"] = {"ms_per_step": 1e3 * sum(t16) / len(t16),
+                                       "ir_iterations": it16, "ir_status": st16,
+                                       "forward_error_cols_0_15": e16,
+                                       "meets_1e-12": e16 is not None and e16 <= 1e-12}
+        log(variant, json.dumps(variants[variant]))
 
     # headline: fastest variant that meets the accuracy target (FP64 if none does)
     ok = [p for p, v in variants.items() if v["meets_1e-12"] or x_ref is None]
-    head = min(ok, key=lambda p: variants[p]["ms_per_step"]) if ok else "fp64"
-    hv = variants[head]
+    head_variant = min(ok, key=lambda p: variants[p]["ms_per_step"]) if ok else "fp64"
+    hv = variants[head_variant]
+    head = head_variant.partition("-")[0]          # its Schur precision
 
     # roofline for the dominant kernel of the headline variant
     ph = hv["phase_ms_per_factor"]
@@ -321,10 +473,18 @@ def main():
         log("serving: %d requests" % args.serving_requests)
         serving_out = serving_bench(args.serving_requests, args.seed)
 
+    calu = None
+    if args.calu_n > 0:
+        del A, A0
+        torch.cuda.empty_cache()
+        log("CALU_PRRP n=%d" % args.calu_n)
+        calu = calu_bench(args.calu_n, 128, 512, tau, args.seed, max(1, min(3, args.steps)), 1)
+        log("calu", json.dumps(calu))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d panels" % args.cpu_panels)
-        cpu = cpu_baseline(A0.cpu().numpy(), b, tau, args.cpu_panels)
+        cpu = cpu_baseline(A_host, b, tau, args.cpu_panels)
 
     out = {
         "metric": METRIC, "value": hv["tflops_to_solution"], "unit": "TFLOP/s", "n_gpus": 1,
@@ -333,14 +493,16 @@ def main():
         "dtype": "f64" if head == "fp64" else ("f64+f32" if head == "fp32" else "f64+bf16"),
         "data": "synthetic",
         "config": {"workload": "LU_PRRP factor + refinement to 1e-12, n=%d, b=%d, tau=%g, "
-                               "U diag(s) V^T (Haar U,V; s log-spaced 1..1e-6), 1 rhs; Schur %s"
-                               % (n, b, tau, head),
-                   "n": n, "b": b, "tau": tau, "schur_precision": head, "nrhs": 1},
+                               "U diag(s) V^T (Haar U,V; s log-spaced 1..1e-6), 1 rhs; variant %s"
+                               % (n, b, tau, head_variant),
+                   "n": n, "b": b, "tau": tau, "schur_precision": head, "variant": head_variant,
+                   "nrhs": 1},
         "roofline": roof,
         "cpu_baseline": cpu,
         "variants": variants,
         "solves": solves,
         "serving": serving_out,
+        "calu_prrp": calu,
     }
     print(json.dumps(out), flush=True)
 

@@ -176,6 +176,37 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
                       double tol, int max_iter, int32_t* iters, double* final_rel,
                       int32_t* status, void* workspace, size_t ws_bytes, void* stream);
 
+/* Workspace bytes for prrp_refine_gmres with at most max_inner (1..128)
+ * Krylov vectors per correction.  Host-only. */
+int prrp_gmres_workspace_size(int64_t n, int max_inner, size_t* bytes);
+
+/* GMRES-based refinement of the solution of A x = b (one right-hand side):
+ * each correction solves A d = r by GMRES preconditioned on the left by the
+ * LU factors (Carson and Higham, SIAM J. Sci. Comput. 40, 2018) instead of
+ * by one triangular solve -- the refinement for factors whose Schur updates
+ * ran in low precision.  r = b - A x is formed as if in twice the working
+ * precision (prrp_residual); the Arnoldi basis is orthogonalised by
+ * classical Gram-Schmidt applied twice; GMRES stops when its residual
+ * estimate falls below gmres_tol times its start, or after max_inner steps.
+ * Outer stopping test:
+ *   tol > 0: the correction's size, as prrp_refine (max|d| <= tol max|x|
+ *            converged, a correction that fails to halve stagnated) -- the
+ *            measure a forward-error target needs;
+ *   tol = 0: the componentwise backward error w of equation "comp", as in
+ *            the paper's linear-solver experiments (Section 3.3, Tables
+ *            "bcaluprrp_gepp", "fcaluprrp_gepp"): w <= 2^-53 converged, a
+ *            step that fails to halve w stagnated.
+ * max_outer steps at most (PRRP_IR_CAP).  b, x: device n-vectors (x output).
+ * outer, inner (GMRES steps in all), w_before (w of the unrefined solution),
+ * w_final, final_rel (last max|d|/max|x|), status: host outputs, each may be
+ * NULL.  The call synchronizes `stream` once per Arnoldi step.  Returns 0 or
+ * -k for an invalid argument k. */
+int prrp_refine_gmres(const double* A, const double* LU, int64_t n, int64_t lda,
+                      const int64_t* perm, const double* b, double* x, double tol,
+                      double gmres_tol, int max_inner, int max_outer, int* outer, int* inner,
+                      double* w_before, double* w_final, double* final_rel, int* status,
+                      void* workspace, size_t ws_bytes, void* stream);
+
 /* Batched LU_PRRP of `count` independent systems of uneven sizes (the
  * algorithm of Section 2.1 on each).  A plan fixes the problems: A[i] (device,
  * n[i] x n[i], row-major, lda[i]), panel width b[i], perm[i] (device, n[i]

@@ -144,12 +144,18 @@ def gmres(apply_op, rhs: np.ndarray, tol: float, max_it: int, x0: np.ndarray | N
     return x0 + V[:, :k] @ y, k, hist
 
 
-def gmres_ir(A, LU, perm, b, gmres_tol: float = 1e-6, max_inner: int = 60, max_outer: int = 20):
+def gmres_ir(A, LU, perm, b, gmres_tol: float = 1e-6, max_inner: int = 60, max_outer: int = 20,
+             tol: float = 0.0):
     """GMRES-based refinement (Carson and Higham 2018) with the LU factors as
-    left preconditioner and w as the stopping measure.
+    left preconditioner.
 
+    With tol = 0 the stopping measure is w, as in ``refine_w``.  With tol > 0
+    it is the size of the correction, as in ``solve.refine``: stop once
+    ||d||_inf <= tol ||x||_inf, or once it fails to halve -- w at the unit
+    roundoff bounds only the backward error, and the forward error can still
+    be kappa times larger, so a forward-error target needs this measure.
     Returns (x, outer steps, total GMRES steps, w_b, history of w, status)
-    with status as in ``refine_w``."""
+    with status "converged", "stagnated" or "cap"."""
     A = np.asarray(A, dtype=np.float64)
 
     def prec_op(v):
@@ -161,8 +167,9 @@ def gmres_ir(A, LU, perm, b, gmres_tol: float = 1e-6, max_inner: int = 60, max_o
     w_b = w
     hist = []
     inner = 0
-    status = "converged" if w <= U_ROUND else "cap"
+    status = "converged" if (tol == 0.0 and w <= U_ROUND) else "cap"
     steps = 0
+    prev = math.inf
     while status == "cap" and steps < max_outer:
         d, k, _ = gmres(prec_op, solve(LU, perm, r), gmres_tol, max_inner)
         inner += k
@@ -171,7 +178,14 @@ def gmres_ir(A, LU, perm, b, gmres_tol: float = 1e-6, max_inner: int = 60, max_o
         r = residual_dot2(A, x, b)
         w_new = comp_w(A, x, b, r)
         hist.append(w_new)
-        if w_new <= U_ROUND:
+        if tol > 0.0:
+            rel = float(np.abs(d).max() / max(np.abs(x).max(), np.finfo(float).tiny))
+            if rel <= tol:
+                status = "converged"
+            elif not (rel <= 0.5 * prev):
+                status = "stagnated"
+            prev = rel
+        elif w_new <= U_ROUND:
             status = "converged"
         elif not (w_new <= 0.5 * w):
             status = "stagnated"

@@ -8,7 +8,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
-__all__ = ["factor", "calu_factor", "solve", "residual", "refine", "refine_async", "gemm",
+__all__ = ["factor", "calu_factor", "solve", "residual", "refine", "refine_async", "refine_gmres",
+           "gemm",
            "FactorResult", "read_stats", "BatchPlan"]
 
 
@@ -184,6 +185,39 @@ def refine_async(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30, workspa
                                         _stream_ptr())
     _lib.check(code, "prrp_refine_async")
     return X.view(B.shape), it, rel, status
+
+
+def refine_gmres(A, LU, perm, b, tol: float = 1e-14, gmres_tol: float = 1e-8, max_inner: int = 60,
+                 max_outer: int = 20, workspace=None):
+    """GMRES-based refinement (one right-hand side).  tol > 0 stops on the
+    correction's size (max|d| <= tol max|x|), tol = 0 on the componentwise
+    backward error w reaching the unit roundoff.
+
+    Returns (x, outer steps, total GMRES steps, w of the unrefined solution,
+    final w, last max|d|/max|x|, status) with status "converged",
+    "stagnated" or "cap"."""
+    import ctypes
+    from . import _lib
+    torch = _torch()
+    _check_matrix(A)
+    n = A.shape[0]
+    bv = b.contiguous().view(n)
+    x = torch.empty_like(bv)
+    need = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().prrp_gmres_workspace_size(n, int(max_inner), ctypes.byref(need)),
+               "prrp_gmres_workspace_size")
+    if workspace is None or workspace.numel() < need.value:
+        workspace = _alloc(need.value, A.device)
+    outer, inner, st = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    w0, w1, rel = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    code = _lib.lib().prrp_refine_gmres(A.data_ptr(), LU.data_ptr(), n, A.stride(0), perm.data_ptr(),
+                                        bv.data_ptr(), x.data_ptr(), float(tol), float(gmres_tol),
+                                        int(max_inner), int(max_outer), ctypes.byref(outer),
+                                        ctypes.byref(inner), ctypes.byref(w0), ctypes.byref(w1),
+                                        ctypes.byref(rel), ctypes.byref(st), workspace.data_ptr(),
+                                        workspace.numel(), _stream_ptr())
+    _lib.check(code, "prrp_refine_gmres")
+    return x, outer.value, inner.value, w0.value, w1.value, rel.value, _lib.IR_STATUS[st.value]
 
 
 class BatchPlan:

@@ -66,8 +66,33 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, LIB)
+    with open(LIB + ".srchash", "w") as fh:
+        fh.write(source_hash() + "\n")
     return LIB
 
 
+def source_hash() -> str:
+    """Hash of every file the library is built from (and the flags)."""
+    import hashlib
+    h = hashlib.sha256(" ".join(flags()).encode())
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for name in sorted(os.listdir(d)):
+            with open(os.path.join(d, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def is_current() -> bool:
+    """True when libprrp.so was built from the sources as they are now."""
+    try:
+        with open(LIB + ".srchash") as fh:
+            return os.path.exists(LIB) and fh.read().strip() == source_hash()
+    except OSError:
+        return False
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if len(sys.argv) > 1 and sys.argv[1] == "--if-stale":
+        print("libprrp.so current" if is_current() else build(verbose=True))
+    else:
+        print(build(verbose=True))

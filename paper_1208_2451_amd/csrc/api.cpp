@@ -123,7 +123,7 @@ struct Layout {
   size_t slots_set_words = 0;     // words per slot set
   size_t off_slots = 0, off_rounds = 0, off_abort = 0, off_sel = 0, off_lists = 0;
   size_t off_y = 0, off_pl = 0, off_p11 = 0, off_moves = 0, off_lsel = 0;
-  size_t off_panel = 0, off_srcmap = 0, panel_stride = 0;
+  size_t off_panel = 0, off_srcmap = 0, panel_stride = 0, off_winv = 0;
   size_t y_stride = 0, sel_stride = 0;   // the two panels' Y and sel buffers
   size_t total = 0;
   int max_members = 0;            // sum over groups of workgroups in any launch
@@ -163,6 +163,7 @@ Layout make_layout(int64_t n, int b, int method, int64_t tile_rows) {
   L.panel_stride = align_up((size_t)n * b * 8, 256);
   L.off_panel = off;  off += 2 * L.panel_stride;
   L.off_srcmap = off; off += align_up((size_t)n * 4, 256);
+  L.off_winv = off;   off += align_up((size_t)b * b * 8, 256);   // CALU_PRRP root: A11^-1
   L.total = off;
   return L;
 }
@@ -353,6 +354,38 @@ struct Ctx {
     return reinterpret_cast<double*>(ws + L.off_panel + (size_t)parity * L.panel_stride);
   }
   int32_t* srcmap() { return reinterpret_cast<int32_t*>(ws + L.off_srcmap); }
+  double* winv() { return reinterpret_cast<double*>(ws + L.off_winv); }
+  // this panel's Y rows sit at their positions after the moves (the moves
+  // must not carry them again)
+  bool y_final = false;
+
+  // CALU_PRRP after the tournament (Section 3.1): the winners become the
+  // panel's pivots and L_2j = A21 A11^-1, which equals (R11^-1 R12)^T of the
+  // QR without pivoting of the panel transpose with the winners first.  No
+  // step here waits on another workgroup: the moves and the source-row map,
+  // the inverse of the b x b block (one workgroup), and one gathered GEMM
+  // that writes Y at the rows' positions after the moves.
+  hipError_t calu_root(int64_t k0, int bw, const int32_t* winners) {
+    const int64_t m = n - k0;
+    GeppArgs ga{A, lda, k0, bw, (int)m, sel(), PL(), mv(), mv() + 2 * kMaxB, mv() + 4 * kMaxB,
+                stats, p11(), panel_src, b};
+    PhaseScope ps(0, st);
+    hipError_t e = launch_root_prep(ga, winners, sel(), srcmap(), st);
+    if (e != hipSuccess) return e;
+    e = launch_block_inverse(ga, winv(), st);
+    if (e != hipSuccess) return e;
+    if (m > bw) {
+      GemmArgs y{(int)(m - bw), bw, bw, panel_src ? panel_src : A + k0 * lda + k0,
+                 panel_src ? (int64_t)b : lda, winv(), bw, Y() + (size_t)bw * b, b, 1.0, 0.0,
+                 &stats->max_block_L, nullptr, PRRP_FP64};
+      y.a_rows = srcmap();
+      y.gather_rows = (int)m;
+      e = launch_gemm(y, st);
+      if (e != hipSuccess) return e;
+    }
+    y_final = true;
+    return hipSuccess;
+  }
   int32_t* mv() {
     return reinterpret_cast<int32_t*>(ws + L.off_moves +
                                       (size_t)(pidx & 1) * align_up((size_t)(4 * kMaxB + 4) * 4, 256));
@@ -427,8 +460,8 @@ struct Ctx {
         e = launch_plan(ga, st);
       }
       if (e != hipSuccess) return e;
-      MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm, (m > bw) ? Yp : nullptr, b,
-                  0, n, k0, bw, 0};
+      MoveArgs ma{A, lda, n, k0, bw, mv_dst, mv_src, n_moves, perm,
+                  (m > bw && !y_final) ? Yp : nullptr, b, 0, n, k0, bw, 0};
       {
         PhaseScope ps(2, st);
         e = launch_moves(ma, st);
@@ -569,6 +602,7 @@ struct Ctx {
       if (e != hipSuccess) return e;
     }
     panel_src = next_panel;
+    y_final = false;
     ++pidx;
     return hipSuccess;
   }
@@ -616,8 +650,7 @@ int64_t factor_tile_cus(int method, int64_t n, int b, int tree, int64_t tile_row
     const int64_t m = n - k0;
     if (method == 0) { one(m, bw); continue; }
     const Tiles t = tile_bounds(m, tile_rows, bw);
-    one(m, bw);                                    // one tile, or the root's QR
-    if (t.start.size() == 1) continue;
+    if (t.start.size() == 1) { one(m, bw); continue; }   // one tile: LU_PRRP's panel
     int maxlen = 0;
     for (int l : t.len) maxlen = std::max(maxlen, l);
     if (tree == PRRP_TREE_BINARY) {
@@ -700,7 +733,6 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
       a.rpw = (int)((m + a.G - 1) / a.G);
       a.tile_start[0] = 0;
       a.tile_len[0] = (int)m;
-      a.mode = 0;
       a.report_rank = 1;
       a.record_block_L = 1;
       a.sel_out = c.sel();
@@ -722,8 +754,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
         a.G = groups_for_rows(maxlen, c.cap, c.rpw_target);
         a.rpw = (maxlen + a.G - 1) / a.G;
         for (int i = 0; i < ntiles; ++i) { a.tile_start[i] = t.start[i]; a.tile_len[i] = t.len[i]; }
-        a.mode = 0;
-        a.sel_out = cur;
+          a.sel_out = cur;
         PRRP_TRY(c.srrqr(a));
         int level = ntiles;
         while (level > 1) {
@@ -736,7 +767,6 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
           nd.rpw = (2 * bw + nd.G - 1) / nd.G;
           for (int i = 0; i < pairs; ++i) { nd.tile_start[i] = i * 2 * bw; nd.tile_len[i] = 2 * bw; }
           nd.row_list = lists;
-          nd.mode = 0;
           nd.sel_out = nxt;
           PRRP_TRY(c.srrqr(nd));
           level = pairs + (level & 1);
@@ -750,8 +780,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
         a.rpw = (t.len[0] + a.G - 1) / a.G;
         a.tile_start[0] = t.start[0];
         a.tile_len[0] = t.len[0];
-        a.mode = 0;
-        a.sel_out = cur;
+          a.sel_out = cur;
         PRRP_TRY(c.srrqr(a));
         for (int i = 1; i < ntiles; ++i) {
           PRRP_TRY(launch_build_lists(cur, 1, bw, lists, nullptr, 1, t.start[i], t.len[i], c.st));
@@ -763,26 +792,13 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
           nd.tile_start[0] = 0;
           nd.tile_len[0] = len;
           nd.row_list = lists;
-          nd.mode = 0;
           nd.sel_out = nxt;
           PRRP_TRY(c.srrqr(nd));
           std::swap(cur, nxt);
         }
       }
-      // QR of the panel transpose with the winners as pivots (emits M)
-      SrrqrArgs r = base_args(c, k0, bw);
-      r.ngroups = 1;
-      r.G = groups_for_rows(m, c.cap, c.rpw_target);
-      r.rpw = (int)((m + r.G - 1) / r.G);
-      r.tile_start[0] = 0;
-      r.tile_len[0] = (int)m;
-      r.mode = 1;
-      r.sel_in = cur;
-      r.record_block_L = 1;
-      r.sel_out = c.sel();
-      r.Y = c.Y();
-      if (c.side2 != nullptr) { r.plan_mv = c.mv(); r.srcmap = c.srcmap(); }
-      PRRP_TRY(c.srrqr(r));
+      // the winners become the panel's pivots
+      PRRP_TRY(c.calu_root(k0, bw, cur));
     }
     PRRP_TRY(c.finish_panel(k0, bw));
   }
@@ -1087,6 +1103,185 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
   return 0;
 }
 
+
+// ------------------------------------------------ GMRES-based refinement
+namespace {
+constexpr int kGmresMax = 128;     // Krylov vectors per correction
+struct GmresWs {
+  double *V, *t, *z, *zero, *part, *small;
+  // small: c[128] | c2[128] | y[128] | hn | beta | w | minus_one
+  double* c() { return small; }
+  double* c2() { return small + kGmresMax; }
+  double* y() { return small + 2 * kGmresMax; }
+  double* hn() { return small + 3 * kGmresMax; }
+  double* beta() { return small + 3 * kGmresMax + 1; }
+  double* w() { return small + 3 * kGmresMax + 2; }
+  double* minus_one() { return small + 3 * kGmresMax + 3; }
+};
+size_t gmres_extra_bytes(int64_t n, int max_inner) {
+  return align_up((size_t)(max_inner + 1) * n * 8, 256) + 3 * align_up((size_t)n * 8, 256) +
+         align_up((size_t)256 * kGmresMax * 8, 256) + align_up((size_t)(3 * kGmresMax + 8) * 8, 256);
+}
+GmresWs gmres_ws(char* base, int64_t n, int max_inner) {
+  GmresWs g;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { char* p = base + off; off += align_up(bytes, 256); return p; };
+  g.V = reinterpret_cast<double*>(take((size_t)(max_inner + 1) * n * 8));
+  g.t = reinterpret_cast<double*>(take((size_t)n * 8));
+  g.z = reinterpret_cast<double*>(take((size_t)n * 8));
+  g.zero = reinterpret_cast<double*>(take((size_t)n * 8));
+  g.part = reinterpret_cast<double*>(take((size_t)256 * kGmresMax * 8));
+  g.small = reinterpret_cast<double*>(take((size_t)(3 * kGmresMax + 8) * 8));
+  return g;
+}
+uint64_t dbits(double v) { uint64_t u; std::memcpy(&u, &v, 8); return u; }
+}  // namespace
+
+int prrp_gmres_workspace_size(int64_t n, int max_inner, size_t* bytes) {
+  if (n < 1 || n > kMaxN) return -1;
+  if (max_inner < 1 || max_inner > kGmresMax) return -2;
+  if (!bytes) return -3;
+  size_t sws = 0;
+  prrp_solve_workspace_size(n, 1, &sws);
+  *bytes = align_up(sws, 256) + gmres_extra_bytes(n, max_inner);
+  return 0;
+}
+
+int prrp_refine_gmres(const double* A, const double* LU, int64_t n, int64_t lda,
+                      const int64_t* perm, const double* b, double* x, double tol,
+                      double gmres_tol, int max_inner, int max_outer, int* outer, int* inner,
+                      double* w_before, double* w_final, double* final_rel, int* status,
+                      void* workspace, size_t ws_bytes, void* stream) {
+  if (!A) return -1;
+  if (!LU) return -2;
+  if (n < 1 || n > kMaxN) return -3;
+  if (lda < n) return -4;
+  if (!perm) return -5;
+  if (!b) return -6;
+  if (!x) return -7;
+  if (!(tol >= 0.0)) return -8;
+  if (!(gmres_tol >= 0.0) || !(gmres_tol < 1.0)) return -9;
+  if (max_inner < 1 || max_inner > kGmresMax) return -10;
+  if (max_outer < 0) return -11;
+  size_t need = 0;
+  prrp_gmres_workspace_size(n, max_inner, &need);
+  if (!workspace) return -18;
+  if (ws_bytes < need) return -19;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  size_t sws = 0;
+  prrp_solve_workspace_size(n, 1, &sws);
+  char* sw = ws;
+  GmresWs g = gmres_ws(ws + align_up(sws, 256), n, max_inner);
+  SolveWs w(sw, n, 1);
+  const double u = std::ldexp(1.0, -53);
+  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(g.zero), (size_t)n, 0ull, st));
+  PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(g.minus_one()), 1, dbits(-1.0), st));
+  // x0 = U^-1 L^-1 b[perm]; r = b - A x0 and w (equation "comp")
+  int rc = solve_impl(LU, n, lda, perm, b, 1, x, 1, 1, sw, st);
+  if (rc) return rc;
+  auto residual_w = [&](double* wh) -> int {
+    PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(g.w()), 1, 0ull, st));
+    PRRP_TRY(launch_residual_w(A, n, lda, x, 1, b, 1, w.r, 1, 1, g.w(), st));
+    PRRP_TRY(hipMemcpyAsync(wh, g.w(), 8, hipMemcpyDeviceToHost, st));
+    PRRP_TRY(hipStreamSynchronize(st));
+    return 0;
+  };
+  double wcur = 0.0;
+  if ((rc = residual_w(&wcur))) return rc;
+  if (w_before) *w_before = wcur;
+  int stat = (tol == 0.0 && wcur <= u) ? PRRP_IR_CONVERGED : PRRP_IR_CAP;
+  int steps = 0, total_inner = 0;
+  double prev_rel = INFINITY, rel = INFINITY;
+  std::vector<double> H((size_t)(kGmresMax + 1) * kGmresMax, 0.0), cs(kGmresMax), sn(kGmresMax),
+      gv(kGmresMax + 1), hbuf(2 * kGmresMax + 4), yv(kGmresMax);
+  while (stat == PRRP_IR_CAP && steps < max_outer) {
+    // GMRES on U^-1 L^-1 A d = U^-1 L^-1 r (Carson and Higham, 2018)
+    rc = solve_impl(LU, n, lda, perm, w.r, 1, g.z, 1, 1, sw, st);
+    if (rc) return rc;
+    PRRP_TRY(launch_nrm2(g.z, n, g.part, g.beta(), st));
+    double beta = 0.0;
+    PRRP_TRY(hipMemcpyAsync(&beta, g.beta(), 8, hipMemcpyDeviceToHost, st));
+    PRRP_TRY(hipStreamSynchronize(st));
+    if (!(beta > 0.0) || !std::isfinite(beta)) { stat = PRRP_IR_STAGNATED; break; }
+    PRRP_TRY(launch_combine(g.V, n, 0, nullptr, 0.0, g.z, g.beta(), g.V, st));
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int k = 0;
+    for (int j = 0; j < max_inner; ++j) {
+      double* Vj = g.V + (size_t)j * n;
+      double* Vn = g.V + (size_t)(j + 1) * n;
+      // t = -A V_j; q = U^-1 L^-1 t[perm]; w = -q
+      PRRP_TRY(launch_residual(A, n, lda, Vj, 1, g.zero, 1, g.t, 1, 1, nullptr, st));
+      rc = solve_impl(LU, n, lda, perm, g.t, 1, g.t, 1, 1, sw, st);
+      if (rc) return rc;
+      PRRP_TRY(launch_combine(g.V, n, 0, nullptr, 0.0, g.t, g.minus_one(), nullptr, st));
+      // classical Gram-Schmidt, twice
+      PRRP_TRY(launch_dots(g.V, n, j + 1, g.t, g.part, g.c(), 0, st));
+      PRRP_TRY(launch_combine(g.V, n, j + 1, g.c(), -1.0, g.t, nullptr, nullptr, st));
+      PRRP_TRY(launch_dots(g.V, n, j + 1, g.t, g.part, g.c2(), 0, st));
+      PRRP_TRY(launch_combine(g.V, n, j + 1, g.c2(), -1.0, g.t, nullptr, nullptr, st));
+      PRRP_TRY(launch_nrm2(g.t, n, g.part, g.hn(), st));
+      PRRP_TRY(launch_combine(g.V, n, 0, nullptr, 0.0, g.t, g.hn(), Vn, st));
+      PRRP_TRY(hipMemcpyAsync(hbuf.data(), g.small, (2 * kGmresMax) * 8, hipMemcpyDeviceToHost, st));
+      PRRP_TRY(hipMemcpyAsync(hbuf.data() + 2 * kGmresMax, g.hn(), 8, hipMemcpyDeviceToHost, st));
+      PRRP_TRY(hipStreamSynchronize(st));
+      double* Hj = H.data() + (size_t)j;                 // column j, row stride kGmresMax
+      for (int i = 0; i <= j; ++i) Hj[(size_t)i * kGmresMax] = hbuf[i] + hbuf[kGmresMax + i];
+      Hj[(size_t)(j + 1) * kGmresMax] = hbuf[2 * kGmresMax];
+      for (int i = 0; i < j; ++i) {                      // earlier rotations
+        const double a0 = Hj[(size_t)i * kGmresMax], a1 = Hj[(size_t)(i + 1) * kGmresMax];
+        Hj[(size_t)i * kGmresMax] = cs[i] * a0 + sn[i] * a1;
+        Hj[(size_t)(i + 1) * kGmresMax] = -sn[i] * a0 + cs[i] * a1;
+      }
+      const double a0 = Hj[(size_t)j * kGmresMax], a1 = Hj[(size_t)(j + 1) * kGmresMax];
+      const double hyp = std::hypot(a0, a1);
+      cs[j] = hyp > 0.0 ? a0 / hyp : 1.0;
+      sn[j] = hyp > 0.0 ? a1 / hyp : 0.0;
+      Hj[(size_t)j * kGmresMax] = hyp;
+      Hj[(size_t)(j + 1) * kGmresMax] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      k = j + 1;
+      if (std::fabs(gv[j + 1]) <= gmres_tol * beta || hyp == 0.0) break;
+    }
+    total_inner += k;
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = gv[i];
+      for (int c = i + 1; c < k; ++c) acc -= H[(size_t)i * kGmresMax + c] * yv[c];
+      const double d = H[(size_t)i * kGmresMax + i];
+      yv[i] = d != 0.0 ? acc / d : 0.0;
+    }
+    PRRP_TRY(hipMemcpyAsync(g.y(), yv.data(), (size_t)k * 8, hipMemcpyHostToDevice, st));
+    // d = V y into t; x += d with max|d| and max|x| (the correction's size)
+    PRRP_TRY(launch_combine(g.V, n, k, g.y(), 1.0, nullptr, nullptr, g.t, st));
+    PRRP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(g.c2()), 2, 0ull, st));
+    PRRP_TRY(launch_axpy_maxrel(x, 1, g.t, 1, n, 1, g.c2(), nullptr, st));
+    double mx[2] = {0.0, 0.0};
+    PRRP_TRY(hipMemcpyAsync(mx, g.c2(), 16, hipMemcpyDeviceToHost, st));
+    ++steps;
+    double wnew = 0.0;
+    if ((rc = residual_w(&wnew))) return rc;           // synchronizes: mx is in
+    rel = mx[0] / (mx[1] > 0.0 ? mx[1] : 1.0);
+    if (tol > 0.0) {
+      if (rel <= tol) stat = PRRP_IR_CONVERGED;
+      else if (!(rel <= 0.5 * prev_rel)) stat = PRRP_IR_STAGNATED;
+      prev_rel = rel;
+    } else if (wnew <= u) {
+      stat = PRRP_IR_CONVERGED;
+    } else if (!(wnew <= 0.5 * wcur)) {
+      stat = PRRP_IR_STAGNATED;
+    }
+    wcur = wnew;
+  }
+  if (outer) *outer = steps;
+  if (inner) *inner = total_inner;
+  if (w_final) *w_final = wcur;
+  if (final_rel) *final_rel = steps > 0 ? rel : 0.0;
+  if (status) *status = stat;
+  return 0;
+}
+
 }  // extern "C"
 
 // ==========================================================================
@@ -1252,7 +1447,6 @@ void plan_build(BatchPlan& P) {
       a.ngroups = (int)list.size();
       a.G = G;
       a.rpw = (int)((maxm + G - 1) / G);
-      a.mode = 0;
       a.tau_bits = tau_bits(P.tau);
       a.report_rank = 1;
       a.record_block_L = 1;

@@ -16,6 +16,8 @@
 // The update of the next panel's columns gathers: rows of B through a row
 // list (the selected rows, before the moves of Pi_j) and rows of C_in through
 // another (the rows that land at each position), writing C out of place.
+// The CALU_PRRP root gathers the rows of A (the panel rows that land at each
+// position) for Y = A21 A11^-1.
 //
 // MFMA 16x16 operand layout (wave64): A operand lane l holds A[l%16][k-group
 // l/16], B operand lane l holds B[k-group l/16][l%16].  The 4 accumulator
@@ -83,12 +85,15 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int bx, int by) {
   const int a_row = tid / (KS / AV), a_k = (tid % (KS / AV)) * AV;
   const int b_k = tid / (BN / BV), b_n = (tid % (BN / BV)) * BV;
 
+  const int gr = m0 + a_row;
+  const int64_t arow =
+      (gr < M) ? (g.a_rows ? (int64_t)min(max(g.a_rows[gr], 0), g.gather_rows - 1) : (int64_t)gr)
+               : 0;
   auto load_slab = [&](int k0) {
-    const int gr = m0 + a_row;
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int gk = k0 + a_k + v;
-      ra[v] = (gr < M && gk < K) ? g.A[(int64_t)gr * g.lda + gk] : 0.0;
+      ra[v] = (gr < M && gk < K) ? g.A[arow * g.lda + gk] : 0.0;
     }
     const int gk = k0 + b_k;
     const int64_t brow =

@@ -307,6 +307,147 @@ hipError_t launch_plan_batched(const GeppArgs* list, int count, hipStream_t stre
   return hipGetLastError();
 }
 
+// ------------------------------------------- CALU_PRRP tournament root
+// After the tournament the panel's winners are known; the step continues as
+// in LU_PRRP with the block L_2j = A21 A11^-1 (Section 3.1: the QR without
+// pivoting of the panel transpose with the winners first gives
+// (R11^-1 R12)^T, which is the same matrix).  The root does it without a
+// cross-workgroup step: root_prep forms the moves of Pi_j and the source-row
+// map, block_inverse forms W = A11^-1 in one workgroup, and one gathered
+// GEMM writes the rows of Y = A21 W at their positions after the moves.
+
+// sel <- the winners (slot order); the moves of Pi_j as plan_kernel forms
+// them; srcmap[t - bw] = the panel row that lands at position t >= bw.
+__global__ __launch_bounds__(256) void root_prep_kernel(GeppArgs a, const int32_t* winners,
+                                                       int32_t* sel, int32_t* srcmap) {
+  const int tid = threadIdx.x;
+  if (tid < a.bw) sel[tid] = winners[tid];
+  __syncthreads();              // plan_body reads a.sel == sel
+  if (tid < 64) plan_body(a);
+  for (int t = a.bw + tid; t < a.m; t += 256) srcmap[t - a.bw] = t;
+  __syncthreads();
+  const int nm = *a.n_moves;
+  for (int e = a.bw + tid; e < nm; e += 256) {
+    const int d = a.mv_dst[e];
+    if (d >= a.bw && d < a.m) srcmap[d - a.bw] = a.mv_src[e];
+  }
+}
+
+hipError_t launch_root_prep(const GeppArgs& a, const int32_t* winners, int32_t* sel,
+                            int32_t* srcmap, hipStream_t stream) {
+  hipLaunchKernelGGL(root_prep_kernel, dim3(1), dim3(256), 0, stream, a, winners, sel, srcmap);
+  return hipGetLastError();
+}
+
+// W = A11^-1 for the bw x bw block of the selected rows (slot order), by
+// Gauss-Jordan elimination with partial pivoting, in place, in registers.
+// Thread (ty, tx) of a 16 x 16 grid holds rows 8 ty .. 8 ty + 7 and columns
+// 8 tx .. 8 tx + 7.  Step k pivots column k on the unused row p_k with the
+// largest |entry| (tie rule), scales it, and eliminates column k from every
+// other row, storing column p_k of the accumulated inverse transform in place
+// of column k; so at the end S[i][j] = (A11^-1)[q_i][p_j], q the inverse of
+// p.  Two barriers per step; the column, pivot row and keys of a step are
+// double-buffered in LDS.  An exactly zero pivot sets info (the column).
+__global__ __launch_bounds__(256) void block_inverse_kernel(GeppArgs a, double* W) {
+  __shared__ double colk[2][kMaxB];
+  __shared__ double rowp[2][kMaxB];
+  __shared__ uint64_t keys[2][16];
+  __shared__ int pivrow[kMaxB];     // p_k
+  __shared__ int slotof[kMaxB];     // q: the step whose pivot row is i
+  const int bw = a.bw;
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  double S[8][8];
+  bool used[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int i = 8 * ty + r;
+    used[r] = i >= bw;                                  // padding rows never pivot
+    const int64_t sr = i < bw ? min(max(a.sel[i], 0), a.m - 1) : 0;
+    const double* src = a.panel ? a.panel + sr * a.ldp : a.A + (a.k0 + sr) * a.lda + a.k0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int j = 8 * tx + c;
+      S[r][c] = (i < bw && j < bw) ? src[j] : 0.0;
+    }
+  }
+  for (int k = 0; k < bw; ++k) {
+    const int buf = k & 1;
+    const int kt = k >> 3, kc = k & 7;
+    if (tx == kt) {
+      uint64_t best = 0;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        double v = S[r][0];
+#pragma unroll
+        for (int c = 1; c < 8; ++c) v = (c == kc) ? S[r][c] : v;
+        colk[buf][8 * ty + r] = v;
+        const uint64_t key = used[r] ? 0ull : make_key(fabs(v), (uint32_t)(8 * ty + r));
+        best = key > best ? key : best;
+      }
+      keys[buf][ty] = best;
+    }
+    __syncthreads();
+    uint64_t kk = keys[buf][0];
+#pragma unroll
+    for (int t = 1; t < 16; ++t) kk = umax(kk, keys[buf][t]);
+    const int p = (int)key_index(kk);
+    const double pv = colk[buf][p];
+    const bool zero = (kk >> kDropBits) == 0;
+    const double pinv = zero ? 0.0 : 1.0 / pv;
+    if (tid == 0) {
+      pivrow[k] = p;
+      slotof[p] = k;
+      if (zero && a.stats) set_info(a.stats, (int32_t)(a.k0 + k + 1));
+      if (key_nonfinite(kk) && a.stats) set_info(a.stats, -1);
+    }
+    if (ty == (p >> 3)) {
+      const int pr = p & 7;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        double v = S[0][c];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) v = (r == pr) ? S[r][c] : v;
+        rowp[buf][8 * tx + c] = (c == kc && tx == kt) ? pinv : v * pinv;
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) used[r] = used[r] || (r == pr);
+    }
+    __syncthreads();
+    double rp[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) rp[c] = rowp[buf][8 * tx + c];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int i = 8 * ty + r;
+      const double f = colk[buf][i];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const double base = (tx == kt && c == kc) ? 0.0 : S[r][c];
+        S[r][c] = (i == p) ? rp[c] : fma(-f, rp[c], base);
+      }
+    }
+  }
+  __syncthreads();
+  // S[i][j] = W[q_i][p_j]
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int i = 8 * ty + r;
+    if (i >= bw) continue;
+    const int wr = slotof[i];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int j = 8 * tx + c;
+      if (j < bw) W[(int64_t)wr * bw + pivrow[j]] = S[r][c];
+    }
+  }
+}
+
+hipError_t launch_block_inverse(const GeppArgs& a, double* W, hipStream_t stream) {
+  hipLaunchKernelGGL(block_inverse_kernel, dim3(1), dim3(256), 0, stream, a, W);
+  return hipGetLastError();
+}
+
 // Pi11 on the top bw rows: row k0+i takes row k0+p11[i] in the columns left
 // of the panel (32-column strips per workgroup) and in perm (workgroup 0).
 __device__ __forceinline__ void perm_top_body(const PermTopArgs& a, int bx) {

@@ -42,8 +42,6 @@ struct SrrqrArgs {
   int32_t tile_start[kMaxGroups];  // first panel row, or offset into row_list
   int32_t tile_len[kMaxGroups];
   const int32_t* row_list;    // nullable: tile rows are row_list[tile_start + t]
-  int mode;                   // 0 strong RRQR, 1 given pivots (sel_in), emits M only
-  const int32_t* sel_in;      // mode 1: tile positions in pivot order
   uint64_t tau_bits;          // truncated encoding of tau
   int report_rank;            // write rank deficiency into stats->info
   int record_block_L;         // record max |M| into stats->max_block_L
@@ -113,6 +111,13 @@ hipError_t launch_perm_top(const PermTopArgs& a, hipStream_t stream);
 hipError_t launch_perm_top_batched(const PermTopArgs* list, int count, int64_t max_k0,
                                    hipStream_t stream);
 hipError_t launch_gepp(const GeppArgs& a, hipStream_t stream);
+// CALU_PRRP root: sel <- winners, the moves of Pi_j (as launch_plan) and
+// srcmap[t - bw] = the panel row that lands at position t >= bw.
+hipError_t launch_root_prep(const GeppArgs& a, const int32_t* winners, int32_t* sel,
+                            int32_t* srcmap, hipStream_t stream);
+// W = A11^-1 (bw x bw, row-major, ld bw) of the selected rows' panel block
+// (a.sel, slot order), Gauss-Jordan with partial pivoting in one workgroup.
+hipError_t launch_block_inverse(const GeppArgs& a, double* W, hipStream_t stream);
 // U12 = L11^-1 Pi11^T A12 in place (p11 nullable: identity).
 hipError_t launch_trsm_u12(double* A, int64_t lda, int64_t k0, int bw, int64_t nr, double* amax1,
                            double* amax2, const int32_t* p11, hipStream_t stream);
@@ -178,6 +183,7 @@ struct GemmArgs {
   int64_t ldcin;
   const int32_t* c_rows;
   int gather_rows;            // gathered row indices are clamped into [0, gather_rows)
+  const int32_t* a_rows;      // nullable: row i of A is A + a_rows[i] * lda (clamped too)
 };
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream);
 hipError_t launch_gemm_batched(const GemmArgs* list, int count, int max_m, int max_n, int prec,
@@ -204,6 +210,20 @@ hipError_t launch_trsv_blocked(const double* LU, int64_t n, int64_t lda, const d
 hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double* X, int64_t ldx,
                            const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
                            const uint32_t* skip, hipStream_t s);
+// R = B - A X as launch_residual, and wout[r] = the componentwise backward
+// error max_i |R_i| / (|A| |X| + |B|)_i of right-hand side r (wout zeroed by
+// the caller).
+hipError_t launch_residual_w(const double* A, int64_t n, int64_t lda, const double* X,
+                             int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
+                             int64_t nrhs, double* wout, hipStream_t s);
+// Krylov vectors (k contiguous n-vectors V[i], k <= 128): out[i] = V[i] . w
+// (fixed reduction order; part: 256 x 128 doubles of scratch; accumulate adds
+// to out), w (or dst) = w + sign sum_i c[i] V[i] [/ *inv_of], and the 2-norm.
+hipError_t launch_dots(const double* V, int64_t n, int k, const double* w, double* part,
+                       double* out, int accumulate, hipStream_t s);
+hipError_t launch_combine(const double* V, int64_t n, int k, const double* c, double sign,
+                          double* w, const double* inv_of, double* dst, hipStream_t s);
+hipError_t launch_nrm2(const double* w, int64_t n, double* part, double* out, hipStream_t s);
 hipError_t launch_axpy_maxrel(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t n,
                               int64_t nrhs, double* out2, const uint32_t* skip, hipStream_t s);
 

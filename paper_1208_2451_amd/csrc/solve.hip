@@ -225,10 +225,15 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
   e = (a - (s - bb)) + (b - bb);
 }
 
+// With wout non-null it also forms the componentwise backward error of
+// equation "comp": wout[r] = max_i |R_i| / (|A| |X| + |B|)_i over the rows
+// (device maximum; the caller zeroes wout; a zero denominator with a non-zero
+// residual gives +inf).
 __device__ __forceinline__ void residual_body(const double* A, int64_t n, int64_t lda,
                                               const double* X, int64_t ldx, const double* B,
                                               int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
-                                              const uint32_t* skip, int bx) {
+                                              const uint32_t* skip, int bx,
+                                              double* wout = nullptr) {
   if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)bx * 4 + (threadIdx.x >> 6);
@@ -236,11 +241,12 @@ __device__ __forceinline__ void residual_body(const double* A, int64_t n, int64_
   const double* arow = A + row * lda;
   for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RC) {
     const int nr = (int)min<int64_t>(RC, nrhs - rc0);
-    double p[RC], s[RC];
+    double p[RC], s[RC], den[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
       p[r] = (lane == 0 && r < nr) ? B[row * ldb + rc0 + r] : 0.0;
       s[r] = 0.0;
+      den[r] = fabs(p[r]);
     }
     for (int64_t c = lane; c < n; c += 64) {
       const double a = arow[c];
@@ -254,6 +260,7 @@ __device__ __forceinline__ void residual_body(const double* A, int64_t n, int64_
           two_sum(p[r], -h, t, q);
           p[r] = t;
           s[r] += q - e;
+          if (wout) den[r] = fma(fabs(a), fabs(x), den[r]);
         }
       }
     }
@@ -269,8 +276,22 @@ __device__ __forceinline__ void residual_body(const double* A, int64_t n, int64_
         s[r] = s[r] + so + q;
       }
     }
+    if (wout) {
+#pragma unroll
+      for (int r = 0; r < RC; ++r) den[r] = wave_sum(den[r]);
+    }
     if (lane == 0) {
-      for (int r = 0; r < nr; ++r) R[row * ldr + rc0 + r] = p[r] + s[r];
+      for (int r = 0; r < nr; ++r) {
+        const double res = p[r] + s[r];
+        R[row * ldr + rc0 + r] = res;
+        if (wout) {
+          const double num = fabs(res);
+          const double q = den[r] > 0.0 ? num / den[r]
+                                        : (num > 0.0 ? __longlong_as_double(0x7FF0000000000000ll)
+                                                     : 0.0);
+          atomic_max_pos(&wout[rc0 + r], q);
+        }
+      }
     }
   }
 }
@@ -280,6 +301,104 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* A, int64_t 
                                                        int64_t ldb, double* R, int64_t ldr,
                                                        int64_t nrhs, const uint32_t* skip) {
   residual_body(A, n, lda, X, ldx, B, ldb, R, ldr, nrhs, skip, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void residual_w_kernel(const double* A, int64_t n, int64_t lda,
+                                                         const double* X, int64_t ldx,
+                                                         const double* B, int64_t ldb, double* R,
+                                                         int64_t ldr, int64_t nrhs, double* wout) {
+  residual_body(A, n, lda, X, ldx, B, ldb, R, ldr, nrhs, nullptr, blockIdx.x, wout);
+}
+
+hipError_t launch_residual_w(const double* A, int64_t n, int64_t lda, const double* X,
+                             int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr,
+                             int64_t nrhs, double* wout, hipStream_t s) {
+  const int64_t blocks = (n + 3) / 4;
+  hipLaunchKernelGGL(residual_w_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, X,
+                     ldx, B, ldb, R, ldr, nrhs, wout);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- Krylov vector kernels
+// The GMRES corrections keep their basis as k contiguous n-vectors V[i].
+// dots: out[i] = V[i] . w for i < k, reduced in a fixed order (partial sums
+// per block, then one pass over the blocks), so results are reproducible.
+constexpr int kDotBlocks = 256;
+constexpr int kMaxKrylov = 128;
+
+__global__ __launch_bounds__(256) void dots_partial_kernel(const double* V, int64_t n, int k,
+                                                           const double* w, double* part) {
+  __shared__ double red[4][kMaxKrylov];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t chunk = (n + kDotBlocks - 1) / kDotBlocks;
+  const int64_t r0 = blockIdx.x * chunk, r1 = min<int64_t>(n, r0 + chunk);
+  for (int i = 0; i < k; ++i) {
+    double acc = 0.0;
+    for (int64_t r = r0 + tid; r < r1; r += 256) acc = fma(V[(int64_t)i * n + r], w[r], acc);
+    acc = wave_sum_fixed(acc);
+    if (lane == 0) red[wave][i] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < k; i += 256)
+    part[(int64_t)blockIdx.x * kMaxKrylov + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+}
+
+__global__ __launch_bounds__(256) void dots_final_kernel(const double* part, int k, double* out,
+                                                         int accumulate) {
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x & 63; b < kDotBlocks; b += 64) acc += part[(int64_t)b * kMaxKrylov + i];
+  acc = wave_sum_fixed(acc);
+  if (threadIdx.x == 0) out[i] = accumulate ? out[i] + acc : acc;
+}
+
+hipError_t launch_dots(const double* V, int64_t n, int k, const double* w, double* part,
+                       double* out, int accumulate, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  if (k > kMaxKrylov) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(kDotBlocks), dim3(256), 0, s, V, n, k, w, part);
+  hipLaunchKernelGGL(dots_final_kernel, dim3(k), dim3(64), 0, s, part, k, out, accumulate);
+  return hipGetLastError();
+}
+
+// w += sign * sum_i c[i] V[i] (c on the device); with inv_of non-null the
+// result is then divided by *inv_of (zero stays zero); written to dst, or in
+// place when dst is null.
+__global__ __launch_bounds__(256) void combine_kernel(const double* V, int64_t n, int k,
+                                                      const double* c, double sign, double* w,
+                                                      const double* inv_of, double* dst) {
+  __shared__ double cs[kMaxKrylov];
+  for (int i = threadIdx.x; i < k; i += 256) cs[i] = sign * c[i];
+  __syncthreads();
+  const int64_t r = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (r >= n) return;
+  double acc = w ? w[r] : 0.0;
+  for (int i = 0; i < k; ++i) acc = fma(cs[i], V[(int64_t)i * n + r], acc);
+  if (inv_of) {
+    const double d = *inv_of;
+    acc = d != 0.0 ? acc / d : 0.0;
+  }
+  (dst ? dst : w)[r] = acc;
+}
+
+hipError_t launch_combine(const double* V, int64_t n, int k, const double* c, double sign,
+                          double* w, const double* inv_of, double* dst, hipStream_t s) {
+  if (k > kMaxKrylov) return hipErrorInvalidValue;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, V, n, k, c, sign, w,
+                     inv_of, dst);
+  return hipGetLastError();
+}
+
+// out = sqrt(part-reduced w . w)
+__global__ void sqrt_kernel(double* x) {
+  if (threadIdx.x == 0) *x = sqrt(*x);
+}
+hipError_t launch_nrm2(const double* w, int64_t n, double* part, double* out, hipStream_t s) {
+  hipError_t e = launch_dots(w, n, 1, w, part, out, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(64), 0, s, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_residual(const double* A, int64_t n, int64_t lda, const double* X, int64_t ldx,

@@ -22,10 +22,6 @@
 // M = R11^-1 R12 is formed for every unselected row; while the largest |M|
 // (tie: lowest row, then lowest slot) exceeds tau the row takes that slot and
 // M is updated by the rank-one exchange formula.
-//
-// Mode 1 (CALU_PRRP after the tournament) runs the same Householder steps with
-// given pivots -- the QR without pivoting of the panel transpose with the
-// winners first (Section 3.1) -- and only emits M.
 #include "common.h"
 #include "kernels.h"
 
@@ -197,30 +193,32 @@ void srrqr_kernel(SrrqrArgs a) {
 
   // ================================================================ QR steps
   // Step s: (1) every wave rebuilds reflector H_{s-1} from the winner row of
-  // step s-1 (in LDS) and applies it to its unselected rows; (2) squared
-  // norms of the trailing parts, best candidate of the workgroup (barrier);
-  // (3) post it, and every wave polls the G posted keys itself; (4) the
-  // winning row is brought into LDS (barrier).
+  // step s-1 (in LDS), applies it to its unselected rows and, in the same
+  // pass, forms the squared norms of their trailing parts (columns >= s);
+  // the workgroup's best candidate (barrier); (2) post it, and one wave polls
+  // the G posted keys; (3) the winning row is brought into LDS (barrier).
+  // Blocks of 8 columns that lie wholly left of the reflector (kd) or of the
+  // norms (kn) are skipped: the reflector is zero there and the norms mask
+  // them out, so the results are the same bit for bit.
   for (int s = 0; s <= bw; ++s) {
+    const int kn = s >> 3;                  // first block holding a column >= s
+    double nn[RPT][4];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) nn[q][t] = 0.0;
+    // lanes of block kn whose column lies left of s
+    const double cmk = __hiloint2double((l8 + 8 * kn >= s) ? 0x3FF00000 : 0, 0);
     if (s > 0) {
       const int sp = s - 1;
+      const int kd = sp >> 3;               // first block holding a column >= sp
       const int c0 = sp + lane, c1 = sp + lane + 64;
       const double x0 = S.prow[c0];           // zero past bw
       const double x1 = S.prow[c1];
       const double head = S.prow[sp];
-      double alpha, beta;
-      if (a.mode == 0) {
-        // formed by the pivot row's owner while its key travelled
-        alpha = S.scal[4];
-        beta = S.scal[5];
-      } else {
-        const double tail = wave_sum_fixed((lane == 0 ? 0.0 : x0 * x0) + x1 * x1);  // c > sp
-        const double nrm = sqrt(fma(head, head, tail));
-        alpha = (nrm == 0.0) ? 0.0 : -copysign(nrm, head);
-        const double v00 = head - alpha;
-        const double vtv = fma(v00, v00, tail);
-        beta = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-      }
+      // formed by the pivot row's owner while its key travelled
+      const double alpha = S.scal[4];
+      const double beta = S.scal[5];
       const double v0 = head - alpha;
       if (wave == 1) {
         for (int i = lane; i < sp; i += 64) S.R[sp * (sp + 1) / 2 + i] = S.prow[i];
@@ -236,17 +234,47 @@ void srrqr_kernel(SrrqrArgs a) {
       double vr[CPT];
 #pragma unroll
       for (int k = 0; k < CPT; ++k) vr[k] = vw[l8 + 8 * k];
-      // branch-free over the rows (so that their chains interleave); rows
-      // already chosen, and rows past the tile, take f = 0 and keep their values
+      // the rows' chains interleave inside each column block; rows already
+      // chosen, and rows past the tile, take f = 0 and keep their values
+      double dd[RPT][4];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dd[q][t] = 0.0;
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        if (k >= kd) {
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) dd[q][k & 3] = fma(vr[k], x[q][k], dd[q][k & 3]);
+        }
+      }
+      double f[RPT];
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        double dd[4] = {0.0, 0.0, 0.0, 0.0};     // independent chains
+        const double d = sum8((dd[q][0] + dd[q][1]) + (dd[q][2] + dd[q][3]));
+        f[q] = (live[q] && !chosen[q]) ? beta * d : 0.0;
+      }
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) dd[k & 3] = fma(vr[k], x[q][k], dd[k & 3]);
-        const double d = sum8((dd[0] + dd[1]) + (dd[2] + dd[3]));
-        const double f = (live[q] && !chosen[q]) ? beta * d : 0.0;
+      for (int k = 0; k < CPT; ++k) {
+        if (k >= kd) {
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) x[q][k] = fma(-f, vr[k], x[q][k]);
+          for (int q = 0; q < RPT; ++q) {
+            x[q][k] = fma(-f[q], vr[k], x[q][k]);
+            if (k >= kn) {
+              const double xm = (k == kn) ? x[q][k] * cmk : x[q][k];
+              nn[q][k & 3] = fma(xm, xm, nn[q][k & 3]);
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const double xm = (k == 0) ? x[q][k] * cmk : x[q][k];
+          nn[q][k & 3] = fma(xm, xm, nn[q][k & 3]);
+        }
       }
     }
     if (s == bw) break;
@@ -255,24 +283,12 @@ void srrqr_kernel(SrrqrArgs a) {
     int wbad = 0;
     int cq = -1;        // the workgroup's candidate among this thread's rows
     double c_alpha = 0.0, c_beta = 0.0;   // the reflector it would define
-    if (a.mode == 0) {
+    {
       uint64_t best = 0;
-      // 0/1 masks of the trailing columns c >= s, shared by the rows (columns
-      // past bw hold zeros); the high word alone encodes 1.0 or 0.0
-      double cm[CPT];
-#pragma unroll
-      for (int k = 0; k < CPT; ++k)
-        cm[k] = __hiloint2double((l8 + 8 * k >= s) ? 0x3FF00000 : 0, 0);
       double nuq[RPT];
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        double nn[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-          const double xm = x[q][k] * cm[k];
-          nn[k & 3] = fma(xm, xm, nn[k & 3]);
-        }
-        nuq[q] = sum8((nn[0] + nn[1]) + (nn[2] + nn[3]));
+        nuq[q] = sum8((nn[q][0] + nn[q][1]) + (nn[q][2] + nn[q][3]));
         const uint64_t key = (live[q] && !chosen[q]) ? make_key(nuq[q], (uint32_t)tpos[q]) : 0ull;
         best = key > best ? key : best;
       }
@@ -346,8 +362,6 @@ void srrqr_kernel(SrrqrArgs a) {
         if (a.report_rank) set_info(pst, (int32_t)(pk0 + s + 1));
       }
       p = (int)key_index(gkey);
-    } else {
-      p = a.sel_in[s];
     }
 
     // bring the pivot row into LDS
@@ -361,22 +375,18 @@ void srrqr_kernel(SrrqrArgs a) {
 #pragma unroll
           for (int k = 0; k < CPT; ++k) {
             const int c = l8 + 8 * k;
-            if (c < bw) {
-              S.prow[c] = x[q][k];
-              if (a.mode == 1 && multi)
-                st_dev(post_r + (size_t)w * kPostW + 2 + c, (uint64_t)__double_as_longlong(x[q][k]));
-            }
+            if (c < bw) S.prow[c] = x[q][k];
           }
           chosen[q] = true;
         }
       }
-      if (a.mode == 0 && cq >= 0 && l8 == 0) { S.scal[4] = c_alpha; S.scal[5] = c_beta; }
+      if (cq >= 0 && l8 == 0) { S.scal[4] = c_alpha; S.scal[5] = c_beta; }
     } else if (owner < G) {
       if (tid < bw) {
         const uint64_t v = poll_word(post_r + (size_t)owner * kPostW + 2 + tid, a.abort_flag, &wbad);
         S.prow[tid] = __longlong_as_double((long long)v);
       }
-      if (a.mode == 0 && tid >= kThreads - 2) {
+      if (tid >= kThreads - 2) {
         const int j = tid - (kThreads - 2);
         const uint64_t v =
             poll_word(post_r + (size_t)owner * kPostW + 2 + 8 * CPT + j, a.abort_flag, &wbad);
@@ -416,10 +426,9 @@ void srrqr_kernel(SrrqrArgs a) {
   int rounds_used = bw;
   int swaps = 0;
   const bool rank_def = S.flags[1] != 0;
-  const bool need_m = (a.mode == 1) ? (pY != nullptr) : true;
   double mmax_local = 0.0;
 
-  if (need_m && !rank_def && tlen > bw) {
+  if (!rank_def && tlen > bw) {
     // ============================================= M = R11^-1 R12 per row
     if (tid < bw) S.rdiag[tid] = 1.0 / S.R[tid * (tid + 1) / 2 + tid];
     __syncthreads();
@@ -449,7 +458,7 @@ void srrqr_kernel(SrrqrArgs a) {
     }
     // x[q] now holds column M(:, row) for unselected rows (garbage for chosen)
 
-    if (a.mode == 0) {
+    {
       // ========================================== exchange loop (Appendix A)
       if (tid < bw) S.vsh[tid] = 0.0;
       for (int e = 0;; ++e) {
@@ -663,7 +672,7 @@ void srrqr_kernel(SrrqrArgs a) {
 
   // ----------------------------------------------- outputs: Y rows, max|M|
   // (at the rows' positions after Pi_j when the moves were formed here)
-  if (need_m && !rank_def && tlen > bw) {
+  if (!rank_def && tlen > bw) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       if (live[q] && !chosen[q]) {

@@ -1,9 +1,10 @@
 """GPU parity of CALU_PRRP (Section 3.1) against the CPU oracle.
 
 Same bar as LU_PRRP: identical permutation, backward error <= 1e-15 n,
-factors within 1e-9 max|LU|, interchange count and tree height equal, per-step
-growth within (1 + tau b)^(H+1) (checked through the oracle on the same
-pivots), and one tile reproduces LU_PRRP exactly.
+factors within 1e-9 max|LU|, interchange count, tree height and the largest
+block-L entry equal, per-step growth within (1 + tau b)^(H+1) (checked
+through the oracle on the same pivots), and one tile reproduces LU_PRRP
+exactly.
 """
 import numpy as np
 import pytest
@@ -28,6 +29,9 @@ def _compare(A, b, tau, tree, tile_rows, tag=""):
     assert st["tree_height"] == f.tree_height
     assert f.step_growth_ok
     assert st["g_W"] == pytest.approx(f.g_W, rel=1e-9)
+    # the root's block L = A21 A11^-1 (formed here through the inverse of the
+    # winners' block) against the oracle's (R11^-1 R12)^T
+    assert st["max_block_L"] == pytest.approx(f.max_block_L, rel=1e-9)
     return st, f
 
 
