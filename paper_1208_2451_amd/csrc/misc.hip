@@ -33,17 +33,37 @@ __global__ void init_stats_kernel(prrp_stats* st, uint32_t* abort_flag, int tree
   }
 }
 
-// perm = identity; max |A| into max_abs_A and max_abs_W (nonfinite -> info -1)
+// perm = identity; max |A| into max_abs_A and max_abs_W (nonfinite -> info -1).
+// Rows are strided over the workgroups and each row is read by the whole
+// workgroup, two doubles per lane per load.
 __global__ __launch_bounds__(256) void init_factor_kernel(const double* A, int64_t n, int64_t lda,
                                                           int64_t* perm, prrp_stats* st) {
   double m = 0.0;
   bool bad = false;
-  const int64_t total = n * n;
-  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int64_t i = e / n, j = e - i * n;
-    const double v = fabs(A[i * lda + j]);
-    if (!(v <= 1.7976931348623157e308)) bad = true;
-    else m = fmax(m, v);
+  const bool pairs = (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const double* row = A + i * lda;
+    if (pairs) {
+      const double2* r2 = reinterpret_cast<const double2*>(row);
+      const int64_t h = n / 2;
+      for (int64_t j = threadIdx.x; j < h; j += 256) {
+        const double2 v = r2[j];
+        const double a = fabs(v.x), c = fabs(v.y);
+        bad = bad || !(a <= 1.7976931348623157e308) || !(c <= 1.7976931348623157e308);
+        m = fmax(m, fmax(a, c));
+      }
+      if ((n & 1) && threadIdx.x == 0) {
+        const double a = fabs(row[n - 1]);
+        bad = bad || !(a <= 1.7976931348623157e308);
+        m = fmax(m, a);
+      }
+    } else {
+      for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const double a = fabs(row[j]);
+        bad = bad || !(a <= 1.7976931348623157e308);
+        m = fmax(m, a);
+      }
+    }
   }
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) perm[i] = i;
 #pragma unroll
@@ -62,8 +82,7 @@ hipError_t launch_init_factor(const double* A, int64_t n, int64_t lda, int64_t* 
                      panels);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int64_t blocks = (n * n + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
+  int64_t blocks = n < 2048 ? n : 2048;
   hipLaunchKernelGGL(init_factor_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, perm,
                      stats);
   return hipGetLastError();

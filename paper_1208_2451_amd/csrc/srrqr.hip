@@ -193,25 +193,13 @@ void srrqr_kernel(SrrqrArgs a) {
 
   // ================================================================ QR steps
   // Step s: (1) every wave rebuilds reflector H_{s-1} from the winner row of
-  // step s-1 (in LDS), applies it to its unselected rows and, in the same
-  // pass, forms the squared norms of their trailing parts (columns >= s);
-  // the workgroup's best candidate (barrier); (2) post it, and one wave polls
-  // the G posted keys; (3) the winning row is brought into LDS (barrier).
-  // Blocks of 8 columns that lie wholly left of the reflector (kd) or of the
-  // norms (kn) are skipped: the reflector is zero there and the norms mask
-  // them out, so the results are the same bit for bit.
+  // step s-1 (in LDS) and applies it to its unselected rows; (2) squared
+  // norms of the trailing parts, best candidate of the workgroup (barrier);
+  // (3) post it, and every wave polls the G posted keys itself; (4) the
+  // winning row is brought into LDS (barrier).
   for (int s = 0; s <= bw; ++s) {
-    const int kn = s >> 3;                  // first block holding a column >= s
-    double nn[RPT][4];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) nn[q][t] = 0.0;
-    // lanes of block kn whose column lies left of s
-    const double cmk = __hiloint2double((l8 + 8 * kn >= s) ? 0x3FF00000 : 0, 0);
     if (s > 0) {
       const int sp = s - 1;
-      const int kd = sp >> 3;               // first block holding a column >= sp
       const int c0 = sp + lane, c1 = sp + lane + 64;
       const double x0 = S.prow[c0];           // zero past bw
       const double x1 = S.prow[c1];
@@ -234,47 +222,17 @@ void srrqr_kernel(SrrqrArgs a) {
       double vr[CPT];
 #pragma unroll
       for (int k = 0; k < CPT; ++k) vr[k] = vw[l8 + 8 * k];
-      // the rows' chains interleave inside each column block; rows already
-      // chosen, and rows past the tile, take f = 0 and keep their values
-      double dd[RPT][4];
-#pragma unroll
-      for (int q = 0; q < RPT; ++q)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) dd[q][t] = 0.0;
-#pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        if (k >= kd) {
-#pragma unroll
-          for (int q = 0; q < RPT; ++q) dd[q][k & 3] = fma(vr[k], x[q][k], dd[q][k & 3]);
-        }
-      }
-      double f[RPT];
+      // branch-free over the rows (so that their chains interleave); rows
+      // already chosen, and rows past the tile, take f = 0 and keep their values
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        const double d = sum8((dd[q][0] + dd[q][1]) + (dd[q][2] + dd[q][3]));
-        f[q] = (live[q] && !chosen[q]) ? beta * d : 0.0;
-      }
+        double dd[4] = {0.0, 0.0, 0.0, 0.0};     // independent chains
 #pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        if (k >= kd) {
+        for (int k = 0; k < CPT; ++k) dd[k & 3] = fma(vr[k], x[q][k], dd[k & 3]);
+        const double d = sum8((dd[0] + dd[1]) + (dd[2] + dd[3]));
+        const double f = (live[q] && !chosen[q]) ? beta * d : 0.0;
 #pragma unroll
-          for (int q = 0; q < RPT; ++q) {
-            x[q][k] = fma(-f[q], vr[k], x[q][k]);
-            if (k >= kn) {
-              const double xm = (k == kn) ? x[q][k] * cmk : x[q][k];
-              nn[q][k & 3] = fma(xm, xm, nn[q][k & 3]);
-            }
-          }
-        }
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const double xm = (k == 0) ? x[q][k] * cmk : x[q][k];
-          nn[q][k & 3] = fma(xm, xm, nn[q][k & 3]);
-        }
+        for (int k = 0; k < CPT; ++k) x[q][k] = fma(-f, vr[k], x[q][k]);
       }
     }
     if (s == bw) break;
@@ -285,10 +243,22 @@ void srrqr_kernel(SrrqrArgs a) {
     double c_alpha = 0.0, c_beta = 0.0;   // the reflector it would define
     {
       uint64_t best = 0;
+      // 0/1 masks of the trailing columns c >= s, shared by the rows (columns
+      // past bw hold zeros); the high word alone encodes 1.0 or 0.0
+      double cm[CPT];
+#pragma unroll
+      for (int k = 0; k < CPT; ++k)
+        cm[k] = __hiloint2double((l8 + 8 * k >= s) ? 0x3FF00000 : 0, 0);
       double nuq[RPT];
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        nuq[q] = sum8((nn[q][0] + nn[q][1]) + (nn[q][2] + nn[q][3]));
+        double nn[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          const double xm = x[q][k] * cm[k];
+          nn[k & 3] = fma(xm, xm, nn[k & 3]);
+        }
+        nuq[q] = sum8((nn[0] + nn[1]) + (nn[2] + nn[3]));
         const uint64_t key = (live[q] && !chosen[q]) ? make_key(nuq[q], (uint32_t)tpos[q]) : 0ull;
         best = key > best ? key : best;
       }

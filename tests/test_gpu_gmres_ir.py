@@ -73,22 +73,32 @@ def test_plain_refinement_fails_where_gmres_ir_converges_bf16():
     import torch
     import paper_1208_2451_amd as prrp
     n = 512
-    A = inputs.kappa_matrix(n, 5, 1e3)
-    b = inputs.rhs(n, 5, 1)
-    announce("bf16 plain vs gmres refinement n=%d" % n)
-    A0 = torch.from_numpy(A).cuda()
-    Af = A0.clone()
-    r = prrp.factor(Af, 64, 2.0, precision="bf16")
-    bt = torch.from_numpy(b).cuda()
-    x_ref = _x_ref(A, b[:, 0])
-    _, _, rel, status = prrp.refine(A0, Af, r.perm, bt, tol=1e-14, max_iter=40)
-    x, outer, inner, w0, w1, rel, st = prrp.refine_gmres(A0, Af, r.perm, bt[:, 0], tol=1e-14,
-                                                         gmres_tol=1e-8, max_inner=80)
-    torch.cuda.synchronize()
-    err = np.abs(x.cpu().numpy() - x_ref).max() / np.abs(x_ref).max()
-    assert err <= 1e-12, (err, outer, inner, w1, st)
-    assert w1 <= 2 * U
-    assert status != "converged"          # one solve per step does not contract here
+    B = inputs.rhs(n, 5, 1)
+    bt = torch.from_numpy(B).cuda()
+    # the smallest kappa of the list at which one triangular solve per
+    # correction no longer reaches 1e-12 (a few 1e3 to 1e4 for these BF16
+    # factors); GMRES-based refinement must reach it there
+    for kappa in (1e3, 1e4, 3e4):
+        A = inputs.kappa_matrix(n, 5, kappa)
+        announce("bf16 plain vs gmres refinement n=%d kappa=%g" % (n, kappa))
+        A0 = torch.from_numpy(A).cuda()
+        Af = A0.clone()
+        r = prrp.factor(Af, 64, 2.0, precision="bf16")
+        x_ref = _x_ref(A, B[:, 0])
+        Xp, _, relp, status = prrp.refine(A0, Af, r.perm, bt, tol=1e-14, max_iter=40)
+        torch.cuda.synchronize()
+        errp = np.abs(Xp.cpu().numpy()[:, 0] - x_ref).max() / np.abs(x_ref).max()
+        if status == "converged" and errp <= 1e-12:
+            continue
+        x, outer, inner, w0, w1, rel, st = prrp.refine_gmres(A0, Af, r.perm, bt[:, 0], tol=1e-14,
+                                                             gmres_tol=1e-8, max_inner=128,
+                                                             max_outer=20)
+        torch.cuda.synchronize()
+        err = np.abs(x.cpu().numpy() - x_ref).max() / np.abs(x_ref).max()
+        assert err <= 1e-12, (kappa, err, outer, inner, w1, st)
+        assert st == "converged" and w1 <= 2 * U
+        return
+    pytest.fail("plain refinement reached 1e-12 at every kappa of the list")
 
 
 @pytest.mark.timeout(600)
