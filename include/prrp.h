@@ -176,6 +176,24 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
                       double tol, int max_iter, int32_t* iters, double* final_rel,
                       int32_t* status, void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * prrp_refine_async with its scratch taken from a fixed device array inside
+ * the library (prrp_static_scratch_bytes() bytes, 16 MiB, one copy per GPU,
+ * held until the process ends) instead of a workspace argument.  The scratch
+ * holds what prrp_solve_workspace_size(n, nrhs) counts; an n x nrhs beyond it
+ * returns -8 before anything is enqueued.  It allocates nothing and calls no
+ * allocating routine; its first call on a device looks up that device's copy
+ * of the array.  Every call on one GPU shares that GPU's array, which keeps
+ * the last call's contents (each call initialises what it reads first), so
+ * calls that overlap on one GPU race: serialise them (one stream, or events).
+ * Other arguments, results and status as prrp_refine_async. */
+size_t prrp_static_scratch_bytes(void);
+int prrp_refine_async_static(const double* A, const double* LU, int64_t n, int64_t lda,
+                             const int64_t* perm, const double* B, double* X, int64_t nrhs,
+                             int64_t ldx, double tol, int max_iter, int32_t* iters,
+                             double* final_rel, int32_t* status, void* stream);
+
 /* Workspace bytes for prrp_refine_gmres with at most max_inner (1..128)
  * Krylov vectors per correction.  Host-only. */
 int prrp_gmres_workspace_size(int64_t n, int max_inner, size_t* bytes);

@@ -8,7 +8,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
-__all__ = ["factor", "calu_factor", "solve", "residual", "refine", "refine_async", "refine_gmres",
+__all__ = ["factor", "calu_factor", "solve", "residual", "refine", "refine_async",
+           "refine_async_static", "refine_gmres",
            "gemm",
            "FactorResult", "read_stats", "BatchPlan"]
 
@@ -184,6 +185,29 @@ def refine_async(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30, workspa
                                         status.data_ptr(), workspace.data_ptr(), workspace.numel(),
                                         _stream_ptr())
     _lib.check(code, "prrp_refine_async")
+    return X.view(B.shape), it, rel, status
+
+
+def refine_async_static(A, LU, perm, B, tol: float = 1e-14, max_iter: int = 30):
+    """refine_async without any workspace: the library's fixed device scratch
+    (no allocation, usable under graph capture).  Calls that overlap on one
+    GPU race on that scratch.  Returns (X, iters, rel, status) as
+    refine_async (X is allocated here by torch, outside the library)."""
+    from . import _lib
+    torch = _torch()
+    _check_matrix(A)
+    n = A.shape[0]
+    B2 = B.contiguous().view(n, -1)
+    nrhs = B2.shape[1]
+    X = torch.empty_like(B2)
+    it = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rel = torch.zeros(1, dtype=torch.float64, device=A.device)
+    status = torch.zeros(1, dtype=torch.int32, device=A.device)
+    code = _lib.lib().prrp_refine_async_static(A.data_ptr(), LU.data_ptr(), n, A.stride(0),
+                                               perm.data_ptr(), B2.data_ptr(), X.data_ptr(), nrhs,
+                                               nrhs, float(tol), int(max_iter), it.data_ptr(),
+                                               rel.data_ptr(), status.data_ptr(), _stream_ptr())
+    _lib.check(code, "prrp_refine_async_static")
     return X.view(B.shape), it, rel, status
 
 

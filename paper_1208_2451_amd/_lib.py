@@ -51,6 +51,9 @@ _SIGS = {
                            _vp, _sz, _vp]),
     "prrp_refine_async": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _dbl, _i32,
                                  _vp, _vp, _vp, _vp, _sz, _vp]),
+    "prrp_static_scratch_bytes": (_sz, []),
+    "prrp_refine_async_static": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _dbl,
+                                        _i32, _vp, _vp, _vp, _vp]),
     "prrp_gmres_workspace_size": (_i32, [_i64, _i32, ctypes.POINTER(_sz)]),
     "prrp_refine_gmres": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _dbl, _dbl, _i32, _i32,
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_dbl),

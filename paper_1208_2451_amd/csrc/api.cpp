@@ -1104,6 +1104,64 @@ int prrp_refine_async(const double* A, const double* LU, int64_t n, int64_t lda,
 }
 
 
+}  // extern "C"
+
+// ------------------------------------------ refinement without allocation
+// Scratch of the entry point below: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel or copy (on the host it is a stand-in, not a device address):
+// each device's address comes from hipGetSymbolAddress, taken once with that
+// device current.
+namespace {
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+}
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+size_t prrp_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+int prrp_refine_async_static(const double* A, const double* LU, int64_t n, int64_t lda,
+                             const int64_t* perm, const double* B, double* X, int64_t nrhs,
+                             int64_t ldx, double tol, int max_iter, int32_t* iters,
+                             double* final_rel, int32_t* status, void* stream) {
+  if (n < 1 || n > kMaxN) return -3;
+  if (nrhs < 1) return -8;
+  size_t need = 0;
+  prrp_solve_workspace_size(n, nrhs, &need);
+  if (need > kStaticScratchBytes) return -8;     // n x nrhs beyond the static scratch
+  void* ws = nullptr;
+  const hipError_t e = scratch_address(&ws);
+  if (e != hipSuccess) return herr(e);
+  return prrp_refine_async(A, LU, n, lda, perm, B, X, nrhs, ldx, tol, max_iter, iters, final_rel,
+                           status, ws, kStaticScratchBytes, stream);
+}
+
+}  // extern "C"
+
+extern "C" {
+
 // ------------------------------------------------ GMRES-based refinement
 namespace {
 constexpr int kGmresMax = 128;     // Krylov vectors per correction
