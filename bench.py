@@ -265,6 +265,8 @@ def main():
                     help="skip the 16 right-hand-side runs")
     ap.add_argument("--calu-n", type=int, default=16384,
                     help="order of the CALU_PRRP run (0 skips it)")
+    ap.add_argument("--calu-only", action="store_true",
+                    help="run only the CALU_PRRP leg (for kernel traces) and print its JSON")
     ap.add_argument("--host-matrix", action="store_true",
                     help="build the kappa matrix with NumPy on the host (same recipe) and copy it "
                          "in, instead of building it with device QR")
@@ -282,6 +284,11 @@ def main():
 
     import paper_1208_2451_amd as prrp
     from paper_1208_2451_amd import _lib, inputs
+
+    if args.calu_only:
+        print(json.dumps(calu_bench(args.calu_n or 16384, 128, 512, args.tau, args.seed,
+                                    args.steps, args.warmup)), flush=True)
+        return
 
     n, b, tau = args.n, args.b, args.tau
     dev = torch.device("cuda:0")
