@@ -242,6 +242,46 @@ def calu_bench(n: int, b: int, tile_rows: int, tau: float, seed: int, steps: int
     return out
 
 
+def calu_sweep(n: int, b: int, tau: float, seed: int):
+    """Tile-size sweep of CALU_PRRP (binary and flat trees) on one N(0,1)
+    matrix: factor time and growth, with g_W / sqrt(n) beside the bands the
+    paper reports for random matrices (Section 3.3: binary tree between
+    sqrt(n)/2 and 3 sqrt(n)/4, flat tree between sqrt(n)/4 and 3 sqrt(n)/4)."""
+    import math
+    import torch
+    import paper_1208_2451_amd as prrp
+    from paper_1208_2451_amd import _lib
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed + 99)
+    A0 = torch.randn(n, n, generator=g, dtype=torch.float64, device=dev)
+    A = torch.empty_like(A0)
+    out = []
+    for tree, tiles in (("binary", (256, 512, 1024, 2048)), ("flat", (512, 2048))):
+        for tr in tiles:
+            ws = torch.empty(_lib.workspace_size(n, b, 1, tr), dtype=torch.uint8, device=dev)
+            A.copy_(A0)
+            prrp.calu_factor(A, b, tau, tree=tree, tile_rows=tr, workspace=ws)   # warm-up
+            A.copy_(A0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = prrp.calu_factor(A, b, tau, tree=tree, tile_rows=tr, workspace=ws)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            st = r.stats()
+            lo, hi = (0.5, 0.75) if tree == "binary" else (0.25, 0.75)
+            gs = st["g_W"] / math.sqrt(n)
+            out.append({"tree": tree, "tile_rows": tr, "ms": ms,
+                        "tflops": 2.0 * n ** 3 / 3.0 / (ms * 1e-3) / 1e12,
+                        "tree_height": st["tree_height"], "g_W": st["g_W"],
+                        "g_W_over_sqrt_n": gs, "paper_band": [lo, hi],
+                        "in_band": lo <= gs <= hi})
+            del ws
+    del A, A0
+    torch.cuda.empty_cache()
+    return {"n": n, "b": b, "runs": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,6 +527,8 @@ def main():
         log("CALU_PRRP n=%d" % args.calu_n)
         calu = calu_bench(args.calu_n, 128, 512, tau, args.seed, max(1, min(3, args.steps)), 1)
         log("calu", json.dumps(calu))
+        calu["tile_sweep"] = calu_sweep(8192, 128, tau, args.seed)
+        log("calu tile sweep", json.dumps(calu["tile_sweep"]))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -88,6 +88,28 @@ def wright(n: int, h: float = 0.3) -> np.ndarray:
     return A
 
 
+def generalized_wilkinson(n: int, seed: int, r: int = 1) -> np.ndarray:
+    """Generalized Wilkinson matrix (Section 2.3; generator of Appendix F):
+    the identity, plus a strictly lower triangular part that is the
+    transpose of a negative, rank-r semi-separable upper triangle with random
+    entries, plus ones in the last column.  The upper triangle is -u v^T
+    (u, v uniform on [0, 1), n x r, from this seed's stream); each row of it is
+    scaled so that its largest entry right of the diagonal has magnitude
+    n / (n + 1).  The paper's runs drew u, v in Matlab with an unstated seed,
+    so only the order of magnitude of its growth figures carries over."""
+    g = np.random.default_rng(seed)
+    u = g.random((n, r))
+    v = g.random((n, r))
+    T = -np.triu(u @ v.T, 1)
+    for i in range(n - 1):
+        m = np.abs(T[i, i + 1:]).max()
+        if m > 0.0:
+            T[i, i + 1:] /= m * (1.0 + 1.0 / n)
+    A = T.T + np.eye(n)
+    A[: n - 1, n - 1] = 1.0
+    return A
+
+
 def kappa_matrix(n: int, seed: int, kappa: float = 1e6, device: str = "cpu"):
     """U diag(s) V^T with Haar U, V and s_i = kappa^(-i/(n-1)).
 

@@ -6,6 +6,7 @@ per-step growth <= 1 + tau b, CALU_PRRP per-step growth <= (1 + tau b)^(H+1),
 the Schur complement of the pivot rows) and the growth the paper prints for
 the Foster matrix (Table "tab_foster", fixture tests/golden/foster_lu_prrp.txt).
 """
+import math
 import os
 
 import numpy as np
@@ -177,3 +178,22 @@ def test_calu_prrp_first_step_is_schur_complement(tree):
     assert np.allclose(f.LU[b:, b:], S, rtol=1e-11, atol=1e-11)
     # Rows of the first block are the tournament winners.
     assert set(f.perm[:b]) == set(f.panel_sel[0])
+
+
+def test_generalized_wilkinson_structure_and_gepp_growth():
+    # Appendix F: unit diagonal, ones in the last column, a negative strictly
+    # lower triangle whose columns (rows of the generator's upper triangle)
+    # peak at n / (n + 1) in magnitude, zeros elsewhere; on it GEPP's growth
+    # is exponential in n (10^42.8 at n = 256 for this draw), LU_PRRP's is
+    # small
+    n = 256
+    A = inputs.generalized_wilkinson(n, 1)
+    assert np.all(np.diag(A) == 1.0) and np.all(A[:, n - 1] == 1.0)
+    low = np.tril(A, -1)
+    assert np.all(low[np.tril_indices(n, -1)] < 0.0)
+    assert np.all(np.triu(A, 1)[:, : n - 1] == 0.0)
+    peaks = np.abs(low).max(axis=0)[: n - 1]
+    assert np.allclose(peaks, n / (n + 1.0), rtol=1e-14)
+    g = lu.gepp(A, track_growth=True).g_W
+    assert math.log10(g) > 30
+    assert lu.lu_prrp(A, 16, 2.0).g_W < 10.0
