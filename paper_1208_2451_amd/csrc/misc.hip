@@ -46,7 +46,20 @@ __global__ __launch_bounds__(256) void init_factor_kernel(const double* A, int64
     if (pairs) {
       const double2* r2 = reinterpret_cast<const double2*>(row);
       const int64_t h = n / 2;
-      for (int64_t j = threadIdx.x; j < h; j += 256) {
+      // four loads in flight per lane before they are reduced
+      int64_t j = threadIdx.x;
+      for (; j + 768 < h; j += 1024) {
+        double2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = r2[j + 256 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double a = fabs(v[u].x), c = fabs(v[u].y);
+          bad = bad || !(a <= 1.7976931348623157e308) || !(c <= 1.7976931348623157e308);
+          m = fmax(m, fmax(a, c));
+        }
+      }
+      for (; j < h; j += 256) {
         const double2 v = r2[j];
         const double a = fabs(v.x), c = fabs(v.y);
         bad = bad || !(a <= 1.7976931348623157e308) || !(c <= 1.7976931348623157e308);
