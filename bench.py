@@ -162,7 +162,8 @@ def serving_bench(nreq: int, seed: int, rates=(0.3, 0.5, 0.7, 1.0)):
                 "rows_per_wg": tuning["rows_per_wg"],
                 "sweep": [{k: r[k] for k in ("load", "rate_per_s", "requests", "solves_per_s",
                                              "p50_ms", "p99_ms", "not_converged",
-                                             "factor_info_nonzero")} for r in sweep],
+                                             "factor_info_nonzero", "batches",
+                                             "plan_build_ms_mean")} for r in sweep],
                 "kind": "Poisson arrivals at %s x saturated capacity, %d requests each; n uniform "
                         "in {64..2048} step 32, b = min(32, n/4), 1-8 rhs, FP32 Schur + FP64 "
                         "refinement to 1e-14; latency = completion - arrival; headline fields at "

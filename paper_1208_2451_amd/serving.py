@@ -108,6 +108,7 @@ class Server:
             mem_budget = int(0.5 * free)
         self.mem_budget = int(mem_budget)
         self.streams = [torch.cuda.Stream(self.device) for _ in range(int(slots))]
+        self.plan_ms = []         # host time to build each batch's plan
 
     def _launch(self, reqs, stream):
         import torch
@@ -116,9 +117,13 @@ class Server:
             work = [r.A.clone() for r in reqs]
             # one rows-per-workgroup value per batch (that of its largest system)
             rpw = self.rows_per_wg(max(r.n for r in reqs))
+            t0 = time.perf_counter()
             plan = BatchPlan(work, [r.b for r in reqs], tau=self.tau, precision=self.precision,
                              rows_per_wg=rpw, originals=[r.A for r in reqs],
                              rhs=[r.B for r in reqs], tol=self.tol, max_iter=self.max_iter)
+            self.plan_ms.append(1e3 * (time.perf_counter() - t0))
+            # a plan is built for one batch's sizes and run once: capturing it
+            # into a graph would cost more host time than the launches it saves
             plan.run(graph=False)
             ev = torch.cuda.Event()
             ev.record(stream)
@@ -130,6 +135,7 @@ class Server:
         every request is present at time 0 (saturation).  Returns a summary."""
         import torch
         reqs = sorted(reqs, key=lambda r: r.t_arrival)
+        self.plan_ms = []
         waiting, inflight = [], [None] * len(self.streams)
         used = 0
         nxt = 0
@@ -204,6 +210,8 @@ class Server:
             # factorization reported a numerical status: served, but flagged
             "not_converged": int(sum(r.status != "converged" for r in reqs)),
             "factor_info_nonzero": int(sum(r.info != 0 for r in reqs)),
+            "batches": len(self.plan_ms),
+            "plan_build_ms_mean": float(np.mean(self.plan_ms)) if self.plan_ms else 0.0,
         }
 
 
