@@ -30,6 +30,7 @@ namespace {
 
 constexpr int kRoundsMax = kMaxB + kMaxExchange + 2;
 constexpr int kRowsPerWgMax = 128;   // 32 row groups x 4 rows per thread
+constexpr int kRowsOneWg = 256;      // one 1024-thread workgroup (at most 64 columns)
 
 inline uint64_t tau_bits(double tau) {
   uint64_t u;
@@ -87,9 +88,32 @@ int panel_wg_cap() {
   return cap;
 }
 
+// A tile of at most 128 rows, or of at most 256 rows and 64 columns, is held
+// by one workgroup (PRRP_ONE_WG=0 splits it as any other tile): its steps
+// then wait on barriers only.
+bool one_wg_tiles() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = getenv("PRRP_ONE_WG");
+    on = (e && atoi(e) == 0) ? 0 : 1;
+  }
+  return on == 1;
+}
+
+// PRRP_INTERLEAVE=0 keeps each tile's workgroups in consecutive blocks.
+bool interleave_tiles() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = getenv("PRRP_INTERLEAVE");
+    on = (e && atoi(e) == 0) ? 0 : 1;
+  }
+  return on == 1;
+}
+
 // `target` rows per workgroup (64 or 128); the workspace is always sized for
 // the default 64, which gives the most workgroups.
-int groups_for_rows(int64_t rows, int cap, int target = 64) {
+int groups_for_rows(int64_t rows, int cap, int target, int bw) {
+  if (one_wg_tiles() && (rows <= kRowsPerWgMax || (rows <= kRowsOneWg && bw <= 64))) return 1;
   cap = std::min(cap, panel_wg_cap());
   int G = (int)std::min<int64_t>(cap, (rows + target - 1) / target);
   if (G < 1) G = 1;
@@ -133,14 +157,14 @@ struct Layout {
 Layout make_layout(int64_t n, int b, int method, int64_t tile_rows) {
   Layout L;
   const int cap = std::min(256, device_cus());
-  int members = groups_for_rows(n, cap);
+  int members = groups_for_rows(n, cap, 64, b);
   int groups = 1;
   if (method == 1) {
     const int64_t ntiles = (n + tile_rows - 1) / tile_rows;
-    const int Gl = groups_for_rows(std::min<int64_t>(tile_rows + b, n), cap);
+    const int Gl = groups_for_rows(std::min<int64_t>(tile_rows + b, n), cap, 64, b);
     members = std::max<int64_t>(members, ntiles * Gl);
-    members = std::max<int64_t>(members, ((ntiles + 1) / 2) * groups_for_rows(2 * b, cap));
-    members = std::max<int>(members, groups_for_rows(tile_rows + b + b, cap));
+    members = std::max<int64_t>(members, ((ntiles + 1) / 2) * groups_for_rows(2 * b, cap, 64, b));
+    members = std::max<int>(members, groups_for_rows(tile_rows + b + b, cap, 64, b));
     groups = (int)std::max<int64_t>(1, ntiles);
   }
   L.max_members = members;
@@ -406,6 +430,11 @@ struct Ctx {
     a.stats = stats;
     a.abort_flag = abort_flag();
     a.tau_bits = tau_bits(tau);
+    // tiles interleaved over the XCDs when the whole launch fits the device
+    if (a.ngroups > 1 && a.G > 1 && interleave_tiles()) {
+      const int64_t cus = tile_cus(a.ngroups * a.G, a.bw, a.rpw);
+      a.interleave = (cus > 0 && cus <= device_cus()) ? 1 : 0;
+    }
     hipError_t e;
     {
       PhaseScope ps(0, st);
@@ -640,7 +669,7 @@ int64_t factor_tile_cus(int method, int64_t n, int b, int tree, int64_t tile_row
                         int rpw_target, int bpc_given = 0) {
   int64_t need = 0;
   auto one = [&](int64_t rows, int bw) {
-    const int G = groups_for_rows(rows, cap, rpw_target);
+    const int G = groups_for_rows(rows, cap, rpw_target, bw);
     const int rpw = (int)((rows + G - 1) / G);
     const int64_t c = tile_cus(G, bw, rpw, bpc_given);
     need = (c < 0 || need < 0) ? -1 : std::max(need, c);
@@ -729,7 +758,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
     if (method == 0 || t.start.size() == 1) {
       SrrqrArgs a = base_args(c, k0, bw);
       a.ngroups = 1;
-      a.G = groups_for_rows(m, c.cap, c.rpw_target);
+      a.G = groups_for_rows(m, c.cap, c.rpw_target, bw);
       a.rpw = (int)((m + a.G - 1) / a.G);
       a.tile_start[0] = 0;
       a.tile_len[0] = (int)m;
@@ -751,7 +780,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
       if (tree == PRRP_TREE_BINARY) {
         SrrqrArgs a = base_args(c, k0, bw);
         a.ngroups = ntiles;
-        a.G = groups_for_rows(maxlen, c.cap, c.rpw_target);
+        a.G = groups_for_rows(maxlen, c.cap, c.rpw_target, bw);
         a.rpw = (maxlen + a.G - 1) / a.G;
         for (int i = 0; i < ntiles; ++i) { a.tile_start[i] = t.start[i]; a.tile_len[i] = t.len[i]; }
           a.sel_out = cur;
@@ -763,7 +792,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
           PRRP_TRY(launch_build_lists(cur, level, bw, lists, nxt, pairs, -1, 0, c.st));
           SrrqrArgs nd = base_args(c, k0, bw);
           nd.ngroups = pairs;
-          nd.G = groups_for_rows(2 * bw, c.cap, c.rpw_target);
+          nd.G = groups_for_rows(2 * bw, c.cap, c.rpw_target, bw);
           nd.rpw = (2 * bw + nd.G - 1) / nd.G;
           for (int i = 0; i < pairs; ++i) { nd.tile_start[i] = i * 2 * bw; nd.tile_len[i] = 2 * bw; }
           nd.row_list = lists;
@@ -776,7 +805,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
         // flat tree: running candidates stacked over each next whole tile
         SrrqrArgs a = base_args(c, k0, bw);
         a.ngroups = 1;
-        a.G = groups_for_rows(t.len[0], c.cap, c.rpw_target);
+        a.G = groups_for_rows(t.len[0], c.cap, c.rpw_target, bw);
         a.rpw = (t.len[0] + a.G - 1) / a.G;
         a.tile_start[0] = t.start[0];
         a.tile_len[0] = t.len[0];
@@ -787,7 +816,7 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
           SrrqrArgs nd = base_args(c, k0, bw);
           const int len = bw + t.len[i];
           nd.ngroups = 1;
-          nd.G = groups_for_rows(len, c.cap, c.rpw_target);
+          nd.G = groups_for_rows(len, c.cap, c.rpw_target, bw);
           nd.rpw = (len + nd.G - 1) / nd.G;
           nd.tile_start[0] = 0;
           nd.tile_len[0] = len;
@@ -1420,7 +1449,7 @@ void plan_build(BatchPlan& P) {
   auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes, 256); return o; };
   P.slots_begin = off;
   for (auto& q : P.p) {
-    q.Gmax = groups_for_rows(q.n, cap, 64);
+    q.Gmax = groups_for_rows(q.n, cap, 64, q.b);
     q.set_words = (size_t)q.Gmax * kRoundsMax * kPostW;
     q.off_slots = take(2 * q.set_words * 8);
   }
@@ -1465,7 +1494,7 @@ void plan_build(BatchPlan& P) {
       if (k0 >= q.n) continue;
       const int64_t m = q.n - k0;
       const int bw = (int)std::min<int64_t>(q.b, m);
-      cls.push_back({{bw, groups_for_rows(m, cap, P.rpw_target)}, (int)i});
+      cls.push_back({{bw, groups_for_rows(m, cap, P.rpw_target, bw)}, (int)i});
     }
     std::stable_sort(cls.begin(), cls.end(),
                      [](const auto& x, const auto& y) { return x.first < y.first; });

@@ -343,93 +343,116 @@ hipError_t launch_root_prep(const GeppArgs& a, const int32_t* winners, int32_t* 
 // Gauss-Jordan elimination with partial pivoting, in place, in registers.
 // Thread (ty, tx) of a 16 x 16 grid holds rows 8 ty .. 8 ty + 7 and columns
 // 8 tx .. 8 tx + 7.  Step k pivots column k on the unused row p_k with the
-// largest |entry| (tie rule), scales it, and eliminates column k from every
-// other row, storing column p_k of the accumulated inverse transform in place
-// of column k; so at the end S[i][j] = (A11^-1)[q_i][p_j], q the inverse of
-// p.  Two barriers per step; the column, pivot row and keys of a step are
-// double-buffered in LDS.  An exactly zero pivot sets info (the column).
-__global__ __launch_bounds__(256) void block_inverse_kernel(GeppArgs a, double* W) {
+// largest |entry| (tie rule), scales that row by 1 / pivot, and eliminates
+// column k from every other row, storing column p_k of the accumulated
+// inverse transform in place of column k; so at the end
+// S[i][j] = (A11^-1)[q_i][p_j], q the inverse of p.  An exactly zero pivot
+// sets info (the column).
+//
+// The steps run in blocks of 8 with the column inside the block unrolled, so
+// every register index is static.  One step:
+//  (1) the owners of column k (tx == k / 8) post its entries and their rows'
+//      keys, then clear their column-k entries;
+//  (2) after a barrier every thread takes the winning row p; the 16 threads
+//      holding row p post it scaled by 1 / pivot (with 1 / pivot in column
+//      k), clear their copy and post -1 as its column-k entry;
+//  (3) after a second barrier every entry takes S -= f_i r_c, f_i the posted
+//      column-k entry of its row and r the posted row: rows i != p get the
+//      elimination (column k: -f_i / pivot), row p becomes the scaled row.
+constexpr int kInvThreads = 256;
+
+__global__ __launch_bounds__(kInvThreads) void block_inverse_kernel(GeppArgs a, double* W) {
   __shared__ double colk[2][kMaxB];
   __shared__ double rowp[2][kMaxB];
-  __shared__ uint64_t keys[2][16];
+  __shared__ uint64_t wkeys[2][kInvThreads / 64];
   __shared__ int pivrow[kMaxB];     // p_k
   __shared__ int slotof[kMaxB];     // q: the step whose pivot row is i
   const int bw = a.bw;
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
-  double S[8][8];
-  bool used[8];
+  const int wave = tid >> 6;
+  // T[c][r] = entry (8 ty + r, 8 tx + c): one 8-entry array per column, so
+  // that the pivot row's uniform index selects registers directly
+  typedef double col8 __attribute__((ext_vector_type(8)));
+  col8 T[8];
+  unsigned usedm = 0;                                   // bit r: row 8 ty + r is used
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int i = 8 * ty + r;
-    used[r] = i >= bw;                                  // padding rows never pivot
+    if (i >= bw) usedm |= 1u << r;                      // padding rows never pivot
     const int64_t sr = i < bw ? min(max(a.sel[i], 0), a.m - 1) : 0;
     const double* src = a.panel ? a.panel + sr * a.ldp : a.A + (a.k0 + sr) * a.lda + a.k0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int j = 8 * tx + c;
-      S[r][c] = (i < bw && j < bw) ? src[j] : 0.0;
+      T[c][r] = (i < bw && j < bw) ? src[j] : 0.0;
     }
   }
-  for (int k = 0; k < bw; ++k) {
-    const int buf = k & 1;
-    const int kt = k >> 3, kc = k & 7;
-    if (tx == kt) {
+  const int nkt = (bw + 7) >> 3;
+  for (int kt = 0; kt < nkt; ++kt) {
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+      const int k = 8 * kt + kc;
+      if (k >= bw) break;
+      const int buf = k & 1;
+      // (1) column k: its owners post it and their best key
       uint64_t best = 0;
+      if (tx == kt) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        double v = S[r][0];
-#pragma unroll
-        for (int c = 1; c < 8; ++c) v = (c == kc) ? S[r][c] : v;
-        colk[buf][8 * ty + r] = v;
-        const uint64_t key = used[r] ? 0ull : make_key(fabs(v), (uint32_t)(8 * ty + r));
-        best = key > best ? key : best;
+        for (int r = 0; r < 8; ++r) {
+          const double v = T[kc][r];
+          colk[buf][8 * ty + r] = v;
+          const uint64_t key = ((usedm >> r) & 1u) ? 0ull : make_key(fabs(v), (uint32_t)(8 * ty + r));
+          best = key > best ? key : best;
+          T[kc][r] = 0.0;
+        }
       }
-      keys[buf][ty] = best;
-    }
-    __syncthreads();
-    uint64_t kk = keys[buf][0];
-#pragma unroll
-    for (int t = 1; t < 16; ++t) kk = umax(kk, keys[buf][t]);
-    const int p = (int)key_index(kk);
-    const double pv = colk[buf][p];
-    const bool zero = (kk >> kDropBits) == 0;
-    const double pinv = zero ? 0.0 : 1.0 / pv;
-    if (tid == 0) {
-      pivrow[k] = p;
-      slotof[p] = k;
-      if (zero && a.stats) set_info(a.stats, (int32_t)(a.k0 + k + 1));
-      if (key_nonfinite(kk) && a.stats) set_info(a.stats, -1);
-    }
-    if (ty == (p >> 3)) {
-      const int pr = p & 7;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        double v = S[0][c];
-#pragma unroll
-        for (int r = 1; r < 8; ++r) v = (r == pr) ? S[r][c] : v;
-        rowp[buf][8 * tx + c] = (c == kc && tx == kt) ? pinv : v * pinv;
+      best = wave_max_key(best);
+      if ((tid & 63) == 0) wkeys[buf][wave] = best;
+      __syncthreads();
+      // (2) the winning row
+      const uint64_t kk = umax(umax(wkeys[buf][0], wkeys[buf][1]), umax(wkeys[buf][2], wkeys[buf][3]));
+      const int p = __builtin_amdgcn_readfirstlane((int)key_index(kk));
+      const bool zero = (kk >> kDropBits) == 0;
+      if (tid == 0) {
+        pivrow[k] = p;
+        slotof[p] = k;
+        if (zero && a.stats) set_info(a.stats, (int32_t)(a.k0 + k + 1));
+        if (key_nonfinite(kk) && a.stats) set_info(a.stats, -1);
       }
+      if (ty == (p >> 3)) {
+        const double pv = colk[buf][p];
+        const double pinv = zero ? 0.0 : 1.0 / pv;
+        const int pr = p & 7;                 // uniform: indexes registers directly
+        double rv[8];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) used[r] = used[r] || (r == pr);
-    }
-    __syncthreads();
-    double rp[8];
+        for (int c = 0; c < 8; ++c) {
+          rv[c] = T[c][pr];
+          T[c][pr] = 0.0;
+        }
+        usedm |= 1u << pr;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) rp[c] = rowp[buf][8 * tx + c];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int i = 8 * ty + r;
-      const double f = colk[buf][i];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const double base = (tx == kt && c == kc) ? 0.0 : S[r][c];
-        S[r][c] = (i == p) ? rp[c] : fma(-f, rp[c], base);
+        for (int c = 0; c < 8; ++c) rowp[buf][8 * tx + c] = rv[c] * pinv;
+        if (tx == kt) {
+          rowp[buf][k] = pinv;
+          colk[buf][p] = -1.0;
+        }
       }
+      __syncthreads();
+      // (3) the rank-one step
+      double rp[8], f[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) rp[c] = rowp[buf][8 * tx + c];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) f[r] = colk[buf][8 * ty + r];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) T[c][r] = fma(-f[r], rp[c], T[c][r]);
     }
   }
   __syncthreads();
-  // S[i][j] = W[q_i][p_j]
+  // entry (i, j) = W[q_i][p_j]
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int i = 8 * ty + r;
@@ -438,13 +461,13 @@ __global__ __launch_bounds__(256) void block_inverse_kernel(GeppArgs a, double* 
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int j = 8 * tx + c;
-      if (j < bw) W[(int64_t)wr * bw + pivrow[j]] = S[r][c];
+      if (j < bw) W[(int64_t)wr * bw + pivrow[j]] = T[c][r];
     }
   }
 }
 
 hipError_t launch_block_inverse(const GeppArgs& a, double* W, hipStream_t stream) {
-  hipLaunchKernelGGL(block_inverse_kernel, dim3(1), dim3(256), 0, stream, a, W);
+  hipLaunchKernelGGL(block_inverse_kernel, dim3(1), dim3(kInvThreads), 0, stream, a, W);
   return hipGetLastError();
 }
 

@@ -68,9 +68,18 @@ struct SrrqrArgs {
   // at position r >= bw.
   int32_t* plan_mv;           // nullable
   int32_t* srcmap;
+  // Block order: 0 puts a tile's workgroups together (block g * G + w), 1
+  // interleaves the tiles (block w * ngroups + g), so that with ngroups a
+  // multiple of 8 a tile's workgroups share an XCD.  Interleaving needs the
+  // whole launch to fit the device at once: otherwise every tile could hold
+  // some of its workgroups resident while waiting on ones never placed.
+  int interleave;
 };
 hipError_t launch_srrqr(const SrrqrArgs& a, hipStream_t stream);
-size_t srrqr_smem_bytes(int bw);
+// LDS of one workgroup of nt threads (256 or 1024) for a panel of width bw.
+size_t srrqr_smem_bytes(int bw, int nt);
+// Most rows one workgroup holds (a workgroup holding more than 128 rows runs
+// with 1024 threads).
 int srrqr_max_rpw();
 hipError_t srrqr_prepare();   // raise the dynamic LDS limit of every instance
 // Workgroups of the instance for (bw, rows per workgroup) one CU holds at once

@@ -29,8 +29,14 @@ namespace prrp {
 
 namespace {
 
+// Workgroup sizes: 512 threads for up to 64 rows per workgroup, 256 for up
+// to 128; 1024 for a tile of up to 256 rows and at most 64 columns held by
+// one workgroup.  A tile held by one workgroup never waits on device memory:
+// every step's winner is found with barriers.
 constexpr int kThreads = 256;
-constexpr int kRowGroups = kThreads / 8;
+constexpr int kThreadsMid = 512;
+constexpr int kThreadsWide = 1024;      // only for panels of at most 64 columns
+constexpr int kRowsWide = kThreadsWide / 8 * 2;
 
 // Poll a posted word until the sentinel is replaced; bounded.
 __device__ __forceinline__ uint64_t poll_word(const uint64_t* p, const uint32_t* abort_flag,
@@ -47,13 +53,46 @@ __device__ __forceinline__ uint64_t poll_word(const uint64_t* p, const uint32_t*
   return v;
 }
 
+// The largest of the keys posted at base + m * stride for this lane's slots
+// m = lane, lane + 64, ... (m < G <= 256), all polled together; bounded.
+// A failed wait sets *bad (the keys not yet posted then count as 0).
+__device__ __forceinline__ uint64_t poll_keys(const uint64_t* base, size_t stride, int G,
+                                              int lane, const uint32_t* abort_flag, int* bad) {
+  uint64_t v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int m = lane + 64 * j;
+    v[j] = m < G ? ld_dev(base + (size_t)m * stride) : 0ull;
+  }
+  unsigned it = 0;
+  for (;;) {
+    bool wait = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wait = wait || v[j] == kKeySent;
+    if (!wait) break;
+    ++it;
+    if (((it & 255u) == 0u && ld_dev_u32(abort_flag) != 0u) || it > kSpinLimit) {
+      *bad = 1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = v[j] == kKeySent ? 0ull : v[j];
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (v[j] == kKeySent) v[j] = ld_dev(base + (size_t)(lane + 64 * j) * stride);
+  }
+  return umax(umax(v[0], v[1]), umax(v[2], v[3]));
+}
+
 struct Smem {
   double* R;       // R11 packed by columns: R(i,j), i <= j, at j(j+1)/2 + i
   double* vsh;     // [kMaxB] reflector / exchange vector
   double* prow;    // [2 kMaxB] winner's row, zero past bw (unguarded reads)
   double* rdiag;   // [kMaxB] 1 / R(i,i)
   double* scal;    // [8]   4, 5: alpha, beta of the pivot row's reflector
-  uint64_t* red;   // [16]  reduction scratch
+  uint64_t* red;   // [2 waves + 8] reduction scratch: per-wave keys, the
+                   // exchange loop's per-wave keys, the polled maximum
   int* selpos;     // [kMaxB] tile positions in slot order
   double* vw;      // [waves][2 kMaxB] per-wave reflector vectors
   int* flags;      // [8]   0: abort, 1: rank deficient, 2: winner slot,
@@ -63,9 +102,9 @@ struct Smem {
 
 }  // namespace
 
-size_t srrqr_smem_bytes(int bw) {
+size_t srrqr_smem_bytes(int bw, int nt) {
   return sizeof(double) * (size_t)(bw * (bw + 1) / 2 + 4 * kMaxB + 8) +
-         sizeof(double) * (size_t)(kThreads / 64) * 2 * kMaxB + sizeof(uint64_t) * 16 +
+         sizeof(double) * (size_t)(nt / 64) * 2 * kMaxB + sizeof(uint64_t) * (2 * (nt / 64) + 8) +
          sizeof(int) * (2 * kMaxB + 8);
 }
 
@@ -78,9 +117,11 @@ __device__ __forceinline__ int post_width(int bw) {
   return 4 + 8 * cpt;
 }
 
-template <int CPT, int RPT>
-__global__ __launch_bounds__(kThreads, 1)
+template <int CPT, int RPT, int NT>
+__global__ __launch_bounds__(NT, 1)
 void srrqr_kernel(SrrqrArgs a) {
+  constexpr int kRowGroups = NT / 8;
+  constexpr int NW = NT / 64;
   extern __shared__ double smem_raw[];
   const int bw = a.bw;
   Smem S;
@@ -90,14 +131,17 @@ void srrqr_kernel(SrrqrArgs a) {
   S.rdiag = S.prow + 2 * kMaxB;
   S.scal = S.rdiag + kMaxB;
   S.vw = S.scal + 8;
-  S.red = reinterpret_cast<uint64_t*>(S.vw + (kThreads / 64) * 2 * kMaxB);
-  S.selpos = reinterpret_cast<int*>(S.red + 16);
+  S.red = reinterpret_cast<uint64_t*>(S.vw + NW * 2 * kMaxB);
+  S.selpos = reinterpret_cast<int*>(S.red + 2 * NW + 8);
   S.flags = S.selpos + kMaxB;
   S.dest = S.flags + 8;
 
   const int G = a.G;
-  const int g = blockIdx.x / G;
-  const int w = blockIdx.x - g * G;
+  // Interleaved, workgroup w of tile g is block w * ngroups + g: blocks go to
+  // the XCDs in turn, so when ngroups is a multiple of 8 a tile's workgroups
+  // share one XCD, where a posted word reaches a poller sooner.
+  const int g = a.interleave ? (int)blockIdx.x % a.ngroups : (int)blockIdx.x / G;
+  const int w = a.interleave ? (int)blockIdx.x / a.ngroups : (int)blockIdx.x - g * G;
   const int tid = threadIdx.x;
   const int l8 = tid & 7;
   const int rg = tid >> 3;
@@ -137,8 +181,8 @@ void srrqr_kernel(SrrqrArgs a) {
   if (a.probs != nullptr) {
     const SrrqrProblem& P = a.probs[g];
     if (P.clear_base != nullptr) {
-      const int nthr = G * kThreads;
-      const int gt = w * kThreads + tid;
+      const int nthr = G * NT;
+      const int gt = w * NT + tid;
       const int per_post = post_width(P.clear_bw);
       const size_t total = (size_t)(*P.clear_rounds) * P.clear_G * per_post;
       for (size_t e = gt; e < total; e += nthr) {
@@ -148,8 +192,8 @@ void srrqr_kernel(SrrqrArgs a) {
       }
     }
   } else if (a.clear_base != nullptr) {
-    const int nthr = gridDim.x * kThreads;
-    const int gt = blockIdx.x * kThreads + tid;
+    const int nthr = gridDim.x * NT;
+    const int gt = blockIdx.x * NT + tid;
     const int per_post = post_width(a.clear_bw);
     for (int cg = 0; cg < a.clear_ngroups; ++cg) {
       const int used = a.clear_rounds[cg];
@@ -188,7 +232,7 @@ void srrqr_kernel(SrrqrArgs a) {
 
   int bad = 0;
   const bool multi = G > 1;
-  S.prow[tid] = 0.0;             // 256 threads cover 2 kMaxB entries
+  if (tid < 2 * kMaxB) S.prow[tid] = 0.0;
   __syncthreads();
 
   // ================================================================ QR steps
@@ -267,7 +311,7 @@ void srrqr_kernel(SrrqrArgs a) {
       __syncthreads();
       uint64_t wkey = S.red[0];
 #pragma unroll
-      for (int i = 1; i < kThreads / 64; ++i) wkey = umax(wkey, S.red[i]);
+      for (int i = 1; i < NW; ++i) wkey = umax(wkey, S.red[i]);
       uint64_t gkey = wkey;
       uint64_t* post_r = slots + (size_t)s * round_stride;
       // Post my candidate: the key first (it travels while the rest is
@@ -313,13 +357,18 @@ void srrqr_kernel(SrrqrArgs a) {
         // traffic low) and shares the maximum through LDS
         if (wave == 0) {
           uint64_t kv = 0;
-          for (int m = lane; m < G; m += 64)
-            kv = umax(kv, poll_word(post_r + (size_t)m * kPostW, a.abort_flag, &wbad));
+          if (G <= 64) {
+            if (lane < G) kv = poll_word(post_r + (size_t)lane * kPostW, a.abort_flag, &wbad);
+          } else {
+            for (int m0 = 0; m0 < G; m0 += 256)
+              kv = umax(kv, poll_keys(post_r + (size_t)m0 * kPostW, kPostW, min(G - m0, 256), lane,
+                                      a.abort_flag, &wbad));
+          }
           kv = wave_max_key(kv);
-          if (lane == 0) { S.red[8] = kv; S.flags[4] = wbad; }
+          if (lane == 0) { S.red[2 * NW] = kv; S.flags[4] = wbad; }
         }
         __syncthreads();
-        gkey = S.red[8];
+        gkey = S.red[2 * NW];
         wbad = S.flags[4];
       }
       if (gkey == 0 && !wbad) {      // fewer rows than columns: not a valid tile
@@ -356,8 +405,8 @@ void srrqr_kernel(SrrqrArgs a) {
         const uint64_t v = poll_word(post_r + (size_t)owner * kPostW + 2 + tid, a.abort_flag, &wbad);
         S.prow[tid] = __longlong_as_double((long long)v);
       }
-      if (tid >= kThreads - 2) {
-        const int j = tid - (kThreads - 2);
+      if (tid >= NT - 2) {
+        const int j = tid - (NT - 2);
         const uint64_t v =
             poll_word(post_r + (size_t)owner * kPostW + 2 + 8 * CPT + j, a.abort_flag, &wbad);
         S.scal[4 + j] = __longlong_as_double((long long)v);
@@ -384,7 +433,7 @@ void srrqr_kernel(SrrqrArgs a) {
     }
     if (a.plan_mv) {
       if (w == 0 && tid == 0) a.plan_mv[4 * kMaxB] = 0;
-      for (int t = row0 + tid; t < row0 + nloc; t += kThreads)
+      for (int t = row0 + tid; t < row0 + nloc; t += NT)
         if (t >= bw) a.srcmap[t - bw] = t;
     }
   };
@@ -458,7 +507,7 @@ void srrqr_kernel(SrrqrArgs a) {
         __syncthreads();
         uint64_t wkey = S.red[0];
 #pragma unroll
-        for (int i = 1; i < kThreads / 64; ++i) wkey = S.red[i] > wkey ? S.red[i] : wkey;
+        for (int i = 1; i < NW; ++i) wkey = S.red[i] > wkey ? S.red[i] : wkey;
         // the owner of the workgroup's best records its slot and row
         const bool own = (best == wkey && wkey != 0);
         uint64_t* post_r = slots + (size_t)r * round_stride;
@@ -483,16 +532,16 @@ void srrqr_kernel(SrrqrArgs a) {
           }
           if (tid == 0) st_dev(post_r + (size_t)w * kPostW, wkey);
           uint64_t kv = 0;
-          for (int m = tid; m < G; m += kThreads)
+          for (int m = tid; m < G; m += NT)
             kv = umax(kv, poll_word(post_r + (size_t)m * kPostW, a.abort_flag, &bad));
           kv = wave_max_u64(kv);
-          if (lane == 0) S.red[4 + wave] = kv;
+          if (lane == 0) S.red[NW + wave] = kv;
           if (bad) S.flags[0] = 1;
           __syncthreads();
           if (S.flags[0]) break;
-          gkey = S.red[4];
+          gkey = S.red[NW];
 #pragma unroll
-          for (int i = 1; i < kThreads / 64; ++i) gkey = S.red[4 + i] > gkey ? S.red[4 + i] : gkey;
+          for (int i = 1; i < NW; ++i) gkey = S.red[NW + i] > gkey ? S.red[NW + i] : gkey;
           gowner = (int)key_index(gkey) / a.rpw;
         }
         rounds_used = r + 1;
@@ -700,62 +749,81 @@ void srrqr_kernel(SrrqrArgs a) {
 }
 
 // ------------------------------------------------------------- dispatch
-#define PRRP_SRRQR_CASE(C, R)                                                              \
-  if (cpt == C && rpt == R) {                                                              \
-    hipLaunchKernelGGL((srrqr_kernel<C, R>), dim3(a.ngroups * a.G), dim3(kThreads), smem, \
+// Columns per lane (bw rounded up to 8, 16, 32, 64, 128 columns), the
+// workgroup size (1024 threads once a workgroup holds more than 128 rows)
+// and rows per thread.
+struct Shape { int cpt, nt, rpt; };
+// A workgroup of at most 64 rows runs with 512 threads (one row per thread,
+// two waves per SIMD, which hide each other's latencies), one of 65..128
+// rows with 256; PRRP_SRRQR_THREADS=256 or 512 fixes the size for those.
+int mid_threads() {
+  static int nt = -1;
+  if (nt < 0) {
+    const char* e = getenv("PRRP_SRRQR_THREADS");
+    const int v = e ? atoi(e) : 0;
+    nt = (v == kThreads || v == kThreadsMid) ? v : 0;
+  }
+  return nt;
+}
+Shape srrqr_shape(int bw, int rpw) {
+  int cpt = (bw + 7) / 8;
+  cpt = cpt <= 2 ? (cpt <= 1 ? 1 : 2) : (cpt <= 4 ? 4 : (cpt <= 8 ? 8 : 16));
+  int nt = mid_threads();
+  if (nt == 0) nt = rpw <= kThreadsMid / 8 ? kThreadsMid : kThreads;
+  if (rpw > (kThreads / 8) * 4) nt = kThreadsWide;
+  return {cpt, nt, (rpw + nt / 8 - 1) / (nt / 8)};
+}
+
+#define PRRP_SRRQR_SHAPES(X)                                                                  \
+  X(1, 1, kThreads) X(1, 2, kThreads) X(1, 3, kThreads) X(1, 4, kThreads)                   \
+  X(2, 1, kThreads) X(2, 2, kThreads) X(2, 3, kThreads) X(2, 4, kThreads)                   \
+  X(4, 1, kThreads) X(4, 2, kThreads) X(4, 3, kThreads) X(4, 4, kThreads)                   \
+  X(8, 1, kThreads) X(8, 2, kThreads) X(8, 3, kThreads) X(8, 4, kThreads)                   \
+  X(16, 1, kThreads) X(16, 2, kThreads) X(16, 3, kThreads) X(16, 4, kThreads)               \
+  X(1, 1, kThreadsMid) X(1, 2, kThreadsMid) X(2, 1, kThreadsMid) X(2, 2, kThreadsMid)       \
+  X(4, 1, kThreadsMid) X(4, 2, kThreadsMid) X(8, 1, kThreadsMid) X(8, 2, kThreadsMid)       \
+  X(16, 1, kThreadsMid) X(16, 2, kThreadsMid)                                               \
+  X(1, 2, kThreadsWide) X(2, 2, kThreadsWide) X(4, 2, kThreadsWide) X(8, 2, kThreadsWide)
+
+#define PRRP_SRRQR_CASE(C, R, T)                                                           \
+  if (sh.cpt == C && sh.rpt == R && sh.nt == T) {                                          \
+    hipLaunchKernelGGL((srrqr_kernel<C, R, T>), dim3(a.ngroups * a.G), dim3(T), smem,     \
                        stream, a);                                                         \
     return hipGetLastError();                                                              \
   }
 
 hipError_t launch_srrqr(const SrrqrArgs& a, hipStream_t stream) {
-  int cpt = (a.bw + 7) / 8;
-  cpt = cpt <= 2 ? (cpt <= 1 ? 1 : 2) : (cpt <= 4 ? 4 : (cpt <= 8 ? 8 : 16));
-  const int rpt = (a.rpw + kRowGroups - 1) / kRowGroups;
-  const size_t smem = srrqr_smem_bytes(a.bw);
-  PRRP_SRRQR_CASE(1, 1) PRRP_SRRQR_CASE(1, 2) PRRP_SRRQR_CASE(1, 3) PRRP_SRRQR_CASE(1, 4)
-  PRRP_SRRQR_CASE(2, 1) PRRP_SRRQR_CASE(2, 2) PRRP_SRRQR_CASE(2, 3) PRRP_SRRQR_CASE(2, 4)
-  PRRP_SRRQR_CASE(4, 1) PRRP_SRRQR_CASE(4, 2) PRRP_SRRQR_CASE(4, 3) PRRP_SRRQR_CASE(4, 4)
-  PRRP_SRRQR_CASE(8, 1) PRRP_SRRQR_CASE(8, 2) PRRP_SRRQR_CASE(8, 3) PRRP_SRRQR_CASE(8, 4)
-  PRRP_SRRQR_CASE(16, 1) PRRP_SRRQR_CASE(16, 2) PRRP_SRRQR_CASE(16, 3) PRRP_SRRQR_CASE(16, 4)
+  const Shape sh = srrqr_shape(a.bw, a.rpw);
+  const size_t smem = srrqr_smem_bytes(a.bw, sh.nt);
+  PRRP_SRRQR_SHAPES(PRRP_SRRQR_CASE)
   return hipErrorInvalidValue;
 }
 
-int srrqr_max_rpw() { return kRowGroups * 4; }
+int srrqr_max_rpw() { return kRowsWide; }
 
-#define PRRP_SRRQR_OCC(C, R)                                                                \
-  if (cpt == C && rpt == R)                                                                 \
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, srrqr_kernel<C, R>, kThreads, \
-                                                        smem);
+#define PRRP_SRRQR_OCC(C, R, T)                                                               \
+  if (sh.cpt == C && sh.rpt == R && sh.nt == T)                                               \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, srrqr_kernel<C, R, T>, T, smem);
 
 // Workgroups of one instance that a compute unit holds at once.
 hipError_t srrqr_blocks_per_cu(int bw, int rpw, int* blocks) {
-  int cpt = (bw + 7) / 8;
-  cpt = cpt <= 2 ? (cpt <= 1 ? 1 : 2) : (cpt <= 4 ? 4 : (cpt <= 8 ? 8 : 16));
-  const int rpt = (rpw + kRowGroups - 1) / kRowGroups;
-  const size_t smem = srrqr_smem_bytes(bw);
-  PRRP_SRRQR_OCC(1, 1) PRRP_SRRQR_OCC(1, 2) PRRP_SRRQR_OCC(1, 3) PRRP_SRRQR_OCC(1, 4)
-  PRRP_SRRQR_OCC(2, 1) PRRP_SRRQR_OCC(2, 2) PRRP_SRRQR_OCC(2, 3) PRRP_SRRQR_OCC(2, 4)
-  PRRP_SRRQR_OCC(4, 1) PRRP_SRRQR_OCC(4, 2) PRRP_SRRQR_OCC(4, 3) PRRP_SRRQR_OCC(4, 4)
-  PRRP_SRRQR_OCC(8, 1) PRRP_SRRQR_OCC(8, 2) PRRP_SRRQR_OCC(8, 3) PRRP_SRRQR_OCC(8, 4)
-  PRRP_SRRQR_OCC(16, 1) PRRP_SRRQR_OCC(16, 2) PRRP_SRRQR_OCC(16, 3) PRRP_SRRQR_OCC(16, 4)
+  const Shape sh = srrqr_shape(bw, rpw);
+  const size_t smem = srrqr_smem_bytes(bw, sh.nt);
+  PRRP_SRRQR_SHAPES(PRRP_SRRQR_OCC)
   return hipErrorInvalidValue;
 }
 
-#define PRRP_SRRQR_ATTR(C, R)                                                               \
-  e = hipFuncSetAttribute((const void*)srrqr_kernel<C, R>,                                  \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);           \
+#define PRRP_SRRQR_ATTR(C, R, T)                                                            \
+  e = hipFuncSetAttribute((const void*)srrqr_kernel<C, R, T>,                               \
+                          hipFuncAttributeMaxDynamicSharedMemorySize,                       \
+                          (int)srrqr_smem_bytes(kMaxB, T));                                 \
   if (e != hipSuccess) return e;
 
 hipError_t srrqr_prepare() {
   static bool done = false;
   if (done) return hipSuccess;
-  const size_t smem = srrqr_smem_bytes(kMaxB);
   hipError_t e;
-  PRRP_SRRQR_ATTR(1, 1) PRRP_SRRQR_ATTR(1, 2) PRRP_SRRQR_ATTR(1, 3) PRRP_SRRQR_ATTR(1, 4)
-  PRRP_SRRQR_ATTR(2, 1) PRRP_SRRQR_ATTR(2, 2) PRRP_SRRQR_ATTR(2, 3) PRRP_SRRQR_ATTR(2, 4)
-  PRRP_SRRQR_ATTR(4, 1) PRRP_SRRQR_ATTR(4, 2) PRRP_SRRQR_ATTR(4, 3) PRRP_SRRQR_ATTR(4, 4)
-  PRRP_SRRQR_ATTR(8, 1) PRRP_SRRQR_ATTR(8, 2) PRRP_SRRQR_ATTR(8, 3) PRRP_SRRQR_ATTR(8, 4)
-  PRRP_SRRQR_ATTR(16, 1) PRRP_SRRQR_ATTR(16, 2) PRRP_SRRQR_ATTR(16, 3) PRRP_SRRQR_ATTR(16, 4)
+  PRRP_SRRQR_SHAPES(PRRP_SRRQR_ATTR)
   done = true;
   return hipSuccess;
 }
