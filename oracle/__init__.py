@@ -13,6 +13,8 @@ Modules
               RRQR exchange loop (Appendix A, Algorithm "Strong RRQR")
   lu       -- GEPP, LU_PRRP (Section 2.1, Algorithm "LU_PRRP factorization")
               and CALU_PRRP (Section 3.1, tournament pivoting)
+  block_lu -- block parallel and block pairwise LU_PRRP (Section 5,
+              Appendix E): an update at every tree node, and their solve
   solve    -- triangular solves and iterative refinement with an exactly
               rounded residual
   metrics  -- growth factors, backward errors, HPL tests, growth bounds and
@@ -22,4 +24,4 @@ Every function names the passage it follows.  Parity status of each function
 is listed in the module docstrings; all functions are pinned by the CPU tests
 under tests/ (no function is "parity unpinned").
 """
-from . import rules, srrqr, lu, solve, metrics  # noqa: F401
+from . import rules, srrqr, lu, block_lu, solve, metrics  # noqa: F401
