@@ -126,6 +126,48 @@ int calu_prrp_factor(double* A, int64_t n, int64_t lda, int b, double tau, int t
                      int64_t tile_rows, int64_t* perm, prrp_stats* stats, void* workspace,
                      size_t ws_bytes, void* stream, int schur);
 
+/* Block parallel (tree PRRP_TREE_BINARY) and block pairwise (PRRP_TREE_FLAT)
+ * LU_PRRP (Section 5, Appendix E).  Each panel's active rows are cut into
+ * tiles as in calu_prrp_factor; at every node of the reduction tree strong
+ * RRQR of the node's rows selects b of them and every other row r of the node
+ * is eliminated against them at once: with d_r its row of
+ * (R11^-1 R12)^T, row r's columns right of the panel become
+ * row r - d_r [selected rows], and d_r is stored in row r's panel columns.
+ * The root's rows move to the top, the diagonal block is factored by GEPP
+ * (interchanges on entire rows) and U12 = L11^-1 Pi11^T A12; no further
+ * update follows (every row was updated once, at its node).
+ *
+ * On exit A holds U on and above the diagonal, each diagonal block's L11
+ * below its diagonal, and every eliminated row's d_r below the diagonal
+ * blocks, rows in final order; perm[p] (device int64[n]) is the original row
+ * at final position p.  nodes (device int32[node_entries], output) records
+ * the elimination order the solve needs, by final position:
+ *   nodes[0] = P (panels), nodes[1] = MN (nodes per panel, at most),
+ *   nodes[2 + j] = panel j's node count (leaves first, up to the root),
+ *   sel  = nodes + 2 + P:           sel[(j MN + v) b + s] = final position of
+ *                                   node v's s-th selected row (slot order,
+ *                                   the order of d_r's entries), -1 if unused,
+ *   elim = sel + P MN b:            elim[j n + p] = the node of panel j that
+ *                                   eliminated the row at p, -1 if none.
+ * stats: device prrp_stats (output; max_block_L = max |d_r|, max_abs_W the
+ * largest magnitude any updated row or U reached).  Tiles whose strong-RRQR
+ * workgroups the device cannot hold at once return -7.  Sizes from
+ * prrp_block_sizes; returns -10 if node_entries is short, -13 if ws_bytes is. */
+int prrp_block_sizes(int64_t n, int b, int tree, int64_t tile_rows, size_t* ws_bytes,
+                     int64_t* node_entries);
+int prrp_block_factor(double* A, int64_t n, int64_t lda, int b, double tau, int tree,
+                      int64_t tile_rows, int64_t* perm, int32_t* nodes, int64_t node_entries,
+                      prrp_stats* stats, void* workspace, size_t ws_bytes, void* stream);
+
+/* Solve A X = B with the factors of prrp_block_factor: B[perm] swept by every
+ * panel's node eliminations (each a function of the panel's starting values)
+ * and L11^-1 of its pivot rows, then X = U^-1 of the result.  B, X: n x nrhs
+ * row-major (ldb, ldx >= nrhs), distinct or equal.  Workspace as
+ * prrp_solve_workspace_size(n, nrhs). */
+int prrp_block_solve(const double* LU, int64_t n, int64_t lda, int b, const int64_t* perm,
+                     const int32_t* nodes, const double* B, int64_t ldb, double* X, int64_t ldx,
+                     int64_t nrhs, void* workspace, size_t ws_bytes, void* stream);
+
 /* Workspace bytes for prrp_solve / prrp_refine with nrhs right-hand sides. */
 int prrp_solve_workspace_size(int64_t n, int64_t nrhs, size_t* bytes);
 

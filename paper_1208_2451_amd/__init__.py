@@ -8,7 +8,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
-__all__ = ["factor", "calu_factor", "solve", "residual", "refine", "refine_async",
+__all__ = ["factor", "calu_factor", "block_factor", "block_solve", "solve", "residual", "refine",
+           "refine_async",
            "refine_async_static", "refine_gmres",
            "gemm",
            "FactorResult", "read_stats", "BatchPlan"]
@@ -100,6 +101,62 @@ def calu_factor(A, b: int, tau: float = 2.0, tree: str = "binary", tile_rows: in
                                        _lib.PRECISIONS[precision])
     _lib.check(code, "calu_prrp_factor")
     return FactorResult(perm, stats, workspace)
+
+
+@dataclass
+class BlockFactorResult:
+    perm: object        # torch int64 [n] on the device
+    nodes: object       # torch int32 node records on the device (layout in include/prrp.h)
+    stats_raw: object
+    workspace: object
+    b: int
+
+    def stats(self) -> dict:
+        return read_stats(self.stats_raw)
+
+
+def block_factor(A, b: int, tau: float = 2.0, tree: str = "binary", tile_rows: int = 512,
+                 workspace=None) -> BlockFactorResult:
+    """Block parallel (tree="binary") or block pairwise (tree="flat") LU_PRRP
+    of A in place (Section 5, Appendix E)."""
+    from . import _lib
+    torch = _torch()
+    _check_matrix(A)
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    ws_bytes, entries = _lib.block_sizes(n, b, _lib.TREES[tree], tile_rows)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc(ws_bytes, A.device)
+    perm = torch.empty(n, dtype=torch.int64, device=A.device)
+    nodes = torch.empty(entries, dtype=torch.int32, device=A.device)
+    stats = torch.zeros(_lib.STATS_BYTES, dtype=torch.uint8, device=A.device)
+    code = _lib.lib().prrp_block_factor(A.data_ptr(), n, A.stride(0), b, float(tau), _lib.TREES[tree],
+                                        tile_rows, perm.data_ptr(), nodes.data_ptr(), entries,
+                                        stats.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                        _stream_ptr())
+    _lib.check(code, "prrp_block_factor")
+    return BlockFactorResult(perm, nodes, stats, workspace, b)
+
+
+def block_solve(LU, r: BlockFactorResult, B, workspace=None):
+    """x with A x = B from block_factor's factors; returns a new tensor."""
+    from . import _lib
+    _check_matrix(LU, "LU")
+    n = LU.shape[0]
+    Bc = B.contiguous()
+    if Bc.dim() == 1:
+        Bc = Bc.view(n, 1)
+    nrhs = Bc.shape[1]
+    X = Bc.clone()
+    ws_bytes = _lib.solve_workspace_size(n, nrhs)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = _alloc(ws_bytes, LU.device)
+    code = _lib.lib().prrp_block_solve(LU.data_ptr(), n, LU.stride(0), r.b, r.perm.data_ptr(),
+                                       r.nodes.data_ptr(), Bc.data_ptr(), nrhs, X.data_ptr(), nrhs,
+                                       nrhs, workspace.data_ptr(), workspace.numel(), _stream_ptr())
+    _lib.check(code, "prrp_block_solve")
+    return X.view(B.shape)
 
 
 def solve(LU, perm, B, workspace=None):

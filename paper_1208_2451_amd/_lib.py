@@ -44,6 +44,11 @@ _SIGS = {
     "prrp_factor_mixed": (_i32, [_vp, _i64, _i64, _i32, _dbl, _vp, _vp, _vp, _sz, _vp, _i32]),
     "calu_prrp_factor": (_i32, [_vp, _i64, _i64, _i32, _dbl, _i32, _i64, _vp, _vp, _vp, _sz, _vp, _i32]),
     "prrp_solve_workspace_size": (_i32, [_i64, _i64, ctypes.POINTER(_sz)]),
+    "prrp_block_sizes": (_i32, [_i64, _i32, _i32, _i64, ctypes.POINTER(_sz), ctypes.POINTER(_i64)]),
+    "prrp_block_factor": (_i32, [_vp, _i64, _i64, _i32, _dbl, _i32, _i64, _vp, _vp, _i64, _vp, _vp,
+                                 _sz, _vp]),
+    "prrp_block_solve": (_i32, [_vp, _i64, _i64, _i32, _vp, _vp, _vp, _i64, _vp, _i64, _i64, _vp,
+                                _sz, _vp]),
     "prrp_solve": (_i32, [_vp, _i64, _i64, _vp, _vp, _i64, _i64, _vp, _sz, _vp]),
     "prrp_residual": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _vp]),
     "prrp_refine": (_i32, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _dbl, _i32,
@@ -114,6 +119,15 @@ def solve_workspace_size(n: int, nrhs: int) -> int:
     out = ctypes.c_size_t(0)
     check(lib().prrp_solve_workspace_size(n, nrhs, ctypes.byref(out)), "prrp_solve_workspace_size")
     return out.value
+
+
+def block_sizes(n: int, b: int, tree: int, tile_rows: int):
+    """(workspace bytes, int32 entries of the node records) of prrp_block_factor."""
+    ws = ctypes.c_size_t(0)
+    ne = ctypes.c_int64(0)
+    check(lib().prrp_block_sizes(n, b, tree, tile_rows, ctypes.byref(ws), ctypes.byref(ne)),
+          "prrp_block_sizes")
+    return ws.value, ne.value
 
 
 PHASES = ["srrqr", "gepp", "moves", "l21", "u12", "schur", "startup"]

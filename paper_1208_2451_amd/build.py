@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libprrp.so")
-SOURCES = ["srrqr.hip", "gepp.hip", "gemm.hip", "misc.hip", "solve.hip", "api.cpp"]
+SOURCES = ["srrqr.hip", "gepp.hip", "gemm.hip", "misc.hip", "solve.hip", "block.hip", "api.cpp"]
 # The strong-RRQR kernel keeps panel rows in registers; its fully unrolled
 # back substitution must stay unrolled (a partial unroll makes register-array
 # indices dynamic and spills them), which needs a higher pragma limit.

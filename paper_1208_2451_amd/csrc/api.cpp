@@ -845,6 +845,210 @@ int run_factor(int method, double* A, int64_t n, int64_t lda, int b, double tau,
   return 0;
 }
 
+// ------------------------------------- block parallel / block pairwise LU_PRRP
+// Section 5 and Appendix E: the CALU_PRRP workspace plus the lists of each
+// level's left-out rows, the level's GEMM arguments, an identity selection
+// (the diagonal GEPP reads the top block after whole-row moves), and the node
+// records kept by original row until the end.
+struct BlockLayout {
+  Layout L;
+  int panels = 0, max_nodes = 0, elim_stride = 0;
+  size_t off_elim = 0, off_list = 0, off_iota = 0, off_nsel = 0, off_nelim = 0, off_counts = 0,
+         off_inv = 0, total = 0;
+};
+
+int block_max_nodes(int64_t n, int b, int tree, int64_t tile_rows) {
+  const int64_t nt = (int64_t)tile_bounds(n, tile_rows, (int)std::min<int64_t>(b, n)).start.size();
+  if (nt <= 1) return 1;
+  return (int)(tree == PRRP_TREE_BINARY ? 2 * nt - 1 : nt);
+}
+
+BlockLayout make_block_layout(int64_t n, int b, int tree, int64_t tile_rows) {
+  BlockLayout B;
+  B.L = make_layout(n, b, 1, tile_rows);
+  B.panels = (int)((n + b - 1) / b);
+  B.max_nodes = block_max_nodes(n, b, tree, tile_rows);
+  // the longest node: a tile with the remainder it absorbed, or a flat-tree
+  // node (b candidates over a tile)
+  B.elim_stride = (int)std::min<int64_t>(n, tile_rows + 2 * (int64_t)b);
+  size_t off = align_up(B.L.total, 256);
+  B.off_elim = off;   off += align_up((size_t)kMaxGroups * B.elim_stride * 4, 256);
+  B.off_list = off;   off += align_up((size_t)kMaxGroups * sizeof(GemmArgs), 256);
+  B.off_iota = off;   off += align_up((size_t)kMaxB * 4, 256);
+  B.off_nsel = off;   off += align_up((size_t)B.panels * B.max_nodes * kMaxB * 4, 256);
+  B.off_nelim = off;  off += align_up((size_t)B.panels * n * 4, 256);
+  B.off_counts = off; off += align_up((size_t)B.panels * 4, 256);
+  B.off_inv = off;    off += align_up((size_t)n * 4, 256);
+  B.total = off;
+  return B;
+}
+
+int64_t block_nodes_len(int64_t n, int b, int tree, int64_t tile_rows) {
+  const int64_t P = (n + b - 1) / b;
+  return 2 + P + P * block_max_nodes(n, b, tree, tile_rows) * (int64_t)b + P * n;
+}
+
+int run_block_factor(double* A, int64_t n, int64_t lda, int b, double tau, int tree,
+                     int64_t tile_rows, int64_t* perm, int32_t* nodes, prrp_stats* stats,
+                     void* workspace, void* stream) {
+  Ctx c;
+  c.A = A; c.n = n; c.lda = lda; c.b = b; c.tau = tau; c.perm = perm; c.stats = stats;
+  c.ws = static_cast<char*>(workspace);
+  c.st = static_cast<hipStream_t>(stream);
+  c.schur = PRRP_FP64;
+  c.cap = std::min(256, device_cus());
+  const BlockLayout BL = make_block_layout(n, b, tree, tile_rows);
+  c.L = BL.L;
+  PRRP_TRY(srrqr_prepare());
+  const int64_t need_cus = factor_tile_cus(1, n, b, tree, tile_rows, c.cap, c.rpw_target);
+  if (need_cus < 0) return herr(hipErrorInvalidValue);
+  if (need_cus > device_cus()) return -7;
+  char* ws = c.ws;
+  int32_t* elim = reinterpret_cast<int32_t*>(ws + BL.off_elim);
+  GemmArgs* list = reinterpret_cast<GemmArgs*>(ws + BL.off_list);
+  int32_t* iota = reinterpret_cast<int32_t*>(ws + BL.off_iota);
+  int32_t* nsel = reinterpret_cast<int32_t*>(ws + BL.off_nsel);
+  int32_t* nelim = reinterpret_cast<int32_t*>(ws + BL.off_nelim);
+  int32_t* counts = reinterpret_cast<int32_t*>(ws + BL.off_counts);
+  int32_t* inv = reinterpret_cast<int32_t*>(ws + BL.off_inv);
+  const int MN = BL.max_nodes;
+  int height = 0;
+  {
+    const Tiles t0 = tile_bounds(n, tile_rows, (int)std::min<int64_t>(b, n));
+    const int nt = (int)t0.start.size();
+    if (tree == PRRP_TREE_BINARY) { while ((1 << height) < nt) ++height; }
+    else height = nt - 1;
+  }
+  PRRP_TRY(launch_init_factor(A, n, lda, perm, stats, c.abort_flag(), height, BL.panels, c.st));
+  PRRP_TRY(launch_fill_u64(c.slot_set(0), 2 * c.L.slots_set_words, kKeySent, c.st));
+  PRRP_TRY(launch_fill_i32(iota, kMaxB, 0, 1, c.st));
+  PRRP_TRY(launch_fill_i32(nsel, (int64_t)BL.panels * MN * kMaxB, -1, 0, c.st));
+  PRRP_TRY(launch_fill_i32(nelim, (int64_t)BL.panels * n, -1, 0, c.st));
+  PRRP_TRY(launch_fill_i32(counts, BL.panels, 0, 0, c.st));
+
+  for (int64_t k0 = 0, j = 0; k0 < n; k0 += b, ++j) {
+    const int bw = (int)std::min<int64_t>(b, n - k0);
+    const int64_t m = n - k0;
+    int node0 = 0;
+    // a level's strong RRQR (d_r of every left-out row into its panel
+    // columns), then its nodes' records and in-place updates
+    auto level = [&](SrrqrArgs& a) -> int {
+      a.Y = A + k0 * lda + k0;
+      a.ldy = lda;
+      a.report_rank = 1;
+      a.record_block_L = 1;
+      PRRP_TRY(c.srrqr(a));
+      BlockNodeArgs nb{A, lda, k0, n, (int)m, node0, elim, BL.elim_stride, perm,
+                       nsel + (size_t)j * MN * kMaxB, nelim + (size_t)j * n, counts + j, list,
+                       &stats->max_abs_W};
+      PRRP_TRY(launch_block_nodes(a, nb, c.st));
+      int max_m = 0;
+      for (int g = 0; g < a.ngroups; ++g) max_m = std::max(max_m, a.tile_len[g] - bw);
+      const int64_t nr = n - k0 - bw;
+      if (max_m > 0 && nr > 0) {
+        PhaseScope ps(5, c.st);
+        PRRP_TRY(launch_gemm_batched(list, a.ngroups, max_m, (int)nr, PRRP_FP64, c.st));
+      }
+      node0 += a.ngroups;
+      return 0;
+    };
+    Tiles t;
+    if (m > bw) t = tile_bounds(m, tile_rows, bw);
+    int32_t* cur = c.lsel();
+    int32_t* nxt = c.lsel() + (size_t)c.L.max_groups * kMaxB;
+    int32_t* lists = c.lists();
+    if (m <= bw || t.start.size() == 1) {
+      SrrqrArgs a = base_args(c, k0, bw);
+      a.ngroups = 1;
+      a.G = groups_for_rows(m, c.cap, c.rpw_target, bw);
+      a.rpw = (int)((m + a.G - 1) / a.G);
+      a.tile_start[0] = 0;
+      a.tile_len[0] = (int)m;
+      a.sel_out = cur;
+      if (int rc = level(a)) return rc;
+    } else {
+      const int ntiles = (int)t.start.size();
+      if (ntiles > kMaxGroups) return -7;
+      int maxlen = 0;
+      for (int l : t.len) maxlen = std::max(maxlen, l);
+      if (tree == PRRP_TREE_BINARY) {
+        SrrqrArgs a = base_args(c, k0, bw);
+        a.ngroups = ntiles;
+        a.G = groups_for_rows(maxlen, c.cap, c.rpw_target, bw);
+        a.rpw = (maxlen + a.G - 1) / a.G;
+        for (int i = 0; i < ntiles; ++i) { a.tile_start[i] = t.start[i]; a.tile_len[i] = t.len[i]; }
+        a.sel_out = cur;
+        if (int rc = level(a)) return rc;
+        int lv = ntiles;
+        while (lv > 1) {
+          const int pairs = lv / 2;
+          PRRP_TRY(launch_build_lists(cur, lv, bw, lists, nxt, pairs, -1, 0, c.st));
+          SrrqrArgs nd = base_args(c, k0, bw);
+          nd.ngroups = pairs;
+          nd.G = groups_for_rows(2 * bw, c.cap, c.rpw_target, bw);
+          nd.rpw = (2 * bw + nd.G - 1) / nd.G;
+          for (int i = 0; i < pairs; ++i) { nd.tile_start[i] = i * 2 * bw; nd.tile_len[i] = 2 * bw; }
+          nd.row_list = lists;
+          nd.sel_out = nxt;
+          if (int rc = level(nd)) return rc;
+          lv = pairs + (lv & 1);
+          std::swap(cur, nxt);
+        }
+      } else {
+        SrrqrArgs a = base_args(c, k0, bw);
+        a.ngroups = 1;
+        a.G = groups_for_rows(t.len[0], c.cap, c.rpw_target, bw);
+        a.rpw = (t.len[0] + a.G - 1) / a.G;
+        a.tile_start[0] = t.start[0];
+        a.tile_len[0] = t.len[0];
+        a.sel_out = cur;
+        if (int rc = level(a)) return rc;
+        for (int i = 1; i < ntiles; ++i) {
+          PRRP_TRY(launch_build_lists(cur, 1, bw, lists, nullptr, 1, t.start[i], t.len[i], c.st));
+          SrrqrArgs nd = base_args(c, k0, bw);
+          const int len = bw + t.len[i];
+          nd.ngroups = 1;
+          nd.G = groups_for_rows(len, c.cap, c.rpw_target, bw);
+          nd.rpw = (len + nd.G - 1) / nd.G;
+          nd.tile_start[0] = 0;
+          nd.tile_len[0] = len;
+          nd.row_list = lists;
+          nd.sel_out = nxt;
+          if (int rc = level(nd)) return rc;
+          std::swap(cur, nxt);
+        }
+      }
+    }
+    // the root's rows: Pi_j on entire rows (the panel columns too: they hold
+    // the left-out rows' d_r), then GEPP of the top block, Pi11, U12
+    GeppArgs gp{A, lda, k0, bw, (int)m, cur, c.PL(), c.mv(), c.mv() + 2 * kMaxB, c.mv() + 4 * kMaxB,
+                stats, c.p11(), nullptr, b};
+    {
+      PhaseScope ps(2, c.st);
+      PRRP_TRY(launch_plan(gp, c.st));
+      MoveArgs ma{A, lda, n, k0, bw, c.mv(), c.mv() + 2 * kMaxB, c.mv() + 4 * kMaxB, perm, nullptr,
+                  b, 0, n, k0, 0, 0};
+      PRRP_TRY(launch_moves(ma, c.st));
+    }
+    GeppArgs gd = gp;
+    gd.sel = iota;
+    {
+      PhaseScope ps(1, c.st);
+      PRRP_TRY(launch_gepp(gd, c.st));
+      PermTopArgs pt{A, lda, k0, bw, perm, c.p11()};
+      PRRP_TRY(launch_perm_top(pt, c.st));
+    }
+    if (m > bw) {
+      PhaseScope ps(4, c.st);
+      PRRP_TRY(launch_trsm_u12(A, lda, k0, bw, n - k0 - bw, &stats->max_abs_U, &stats->max_abs_W,
+                               c.p11(), c.st));
+    }
+  }
+  BlockRecordArgs ra{perm, n, BL.panels, MN, b, counts, nsel, nelim, inv, nodes};
+  PRRP_TRY(launch_block_records(ra, c.st));
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1007,6 +1211,27 @@ int solve_impl(const double* LU, int64_t n, int64_t lda, const int64_t* perm, co
   // U x = y straight into X
   PRRP_TRY(launch_trsv_blocked(LU, n, lda, w.t2, nrhs, X, ldx, nrhs, 0, w.ticket + 1, nullptr, 0,
                                skip, st));
+  return 0;
+}
+
+// Y = the forward sweep of the block factorization applied to B[perm], then
+// X = U^-1 Y.
+int block_solve_impl(const double* LU, int64_t n, int64_t lda, int b, const int64_t* perm,
+                     const int32_t* nodes, const double* B, int64_t ldb, double* X, int64_t ldx,
+                     int64_t nrhs, char* ws, hipStream_t st) {
+  SolveWs w(ws, n, nrhs);
+  PRRP_TRY(launch_gather_rows(B, ldb, perm, w.t1, nrhs, n, nrhs, w.t2, nrhs, w.ticket, nullptr, st));
+  double* cur = w.t1;
+  double* nxt = w.r;
+  const int P = (int)((n + b - 1) / b);
+  for (int j = 0; j < P; ++j) {
+    BlockForwardArgs fa{LU, lda, n, b, j, nodes, cur, nxt, nrhs, nrhs};
+    PRRP_TRY(launch_block_forward(fa, st));
+    std::swap(cur, nxt);
+  }
+  PRRP_TRY(launch_trsv_blocked(LU, n, lda, cur, nrhs, w.t2, nrhs, nrhs, 0, w.ticket + 1, nullptr, 0,
+                               nullptr, st));
+  PRRP_TRY(launch_copy_rows(w.t2, nrhs, X, ldx, n, nrhs, st));
   return 0;
 }
 }  // namespace
@@ -1868,6 +2093,61 @@ int prrp_batch_plan_results(void* plan, int32_t* iters, double* rels, int32_t* s
 int prrp_batch_plan_destroy(void* plan) {
   plan_free(static_cast<BatchPlan*>(plan));
   return 0;
+}
+
+// ------------------------------------- block parallel / block pairwise LU_PRRP
+int prrp_block_sizes(int64_t n, int b, int tree, int64_t tile_rows, size_t* ws_bytes,
+                     int64_t* node_entries) {
+  if (n < 1 || n > kMaxN) return -1;
+  if (b < 1 || b > kMaxB || b > n) return -2;
+  if (tree != PRRP_TREE_BINARY && tree != PRRP_TREE_FLAT) return -3;
+  if (tile_rows < b + 1) return -4;
+  if ((n + tile_rows - 1) / tile_rows > kMaxGroups) return -4;
+  if (ws_bytes) *ws_bytes = make_block_layout(n, b, tree, tile_rows).total;
+  if (node_entries) *node_entries = block_nodes_len(n, b, tree, tile_rows);
+  return 0;
+}
+
+int prrp_block_factor(double* A, int64_t n, int64_t lda, int b, double tau, int tree,
+                      int64_t tile_rows, int64_t* perm, int32_t* nodes, int64_t node_entries,
+                      prrp_stats* stats, void* workspace, size_t ws_bytes, void* stream) {
+  if (!A) return -1;
+  if (n < 1 || n > kMaxN) return -2;
+  if (lda < n) return -3;
+  if (b < 1 || b > kMaxB || b > n) return -4;
+  if (!(tau > 1.0) || !std::isfinite(tau)) return -5;
+  if (tree != PRRP_TREE_BINARY && tree != PRRP_TREE_FLAT) return -6;
+  if (tile_rows < b + 1 || (n + tile_rows - 1) / tile_rows > kMaxGroups) return -7;
+  if (!perm) return -8;
+  if (!nodes) return -9;
+  if (node_entries < block_nodes_len(n, b, tree, tile_rows)) return -10;
+  if (!stats) return -11;
+  if (!workspace) return -12;
+  if (ws_bytes < make_block_layout(n, b, tree, tile_rows).total) return -13;
+  return run_block_factor(A, n, lda, b, tau, tree, tile_rows, perm, nodes, stats, workspace,
+                          stream);
+}
+
+int prrp_block_solve(const double* LU, int64_t n, int64_t lda, int b, const int64_t* perm,
+                     const int32_t* nodes, const double* B, int64_t ldb, double* X, int64_t ldx,
+                     int64_t nrhs, void* workspace, size_t ws_bytes, void* stream) {
+  if (!LU) return -1;
+  if (n < 1 || n > kMaxN) return -2;
+  if (lda < n) return -3;
+  if (b < 1 || b > kMaxB || b > n) return -4;
+  if (!perm) return -5;
+  if (!nodes) return -6;
+  if (!B) return -7;
+  if (nrhs < 1) return -11;
+  if (ldb < nrhs) return -8;
+  if (!X) return -9;
+  if (ldx < nrhs) return -10;
+  size_t need = 0;
+  prrp_solve_workspace_size(n, nrhs, &need);
+  if (!workspace) return -12;
+  if (ws_bytes < need) return -13;
+  return block_solve_impl(LU, n, lda, b, perm, nodes, B, ldb, X, ldx, nrhs,
+                          static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -197,10 +197,9 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int bx, int by) {
         const int c = n0 + wn * (BN / WN) + j * 16 + li;
         if (r < M && c < N) {
           const double p = (sizeof(T) == 8) ? accd[i][j][v] : (double)accf[i][j][v];
-          double* cp = g.C + (int64_t)r * g.ldc + c;
-          const double* cin =
-              g.Cin ? g.Cin + (int64_t)min(max(g.c_rows[r], 0), g.gather_rows - 1) * g.ldcin + c
-                    : cp;
+          const int64_t gcr = g.Cin ? (int64_t)min(max(g.c_rows[r], 0), g.gather_rows - 1) : r;
+          double* cp = g.C + (g.c_scatter ? gcr : (int64_t)r) * g.ldc + c;
+          const double* cin = g.Cin ? g.Cin + gcr * g.ldcin + c : cp;
           const double val = (g.beta != 0.0) ? fma(g.alpha, p, g.beta * *cin) : g.alpha * p;
           *cp = val;
           amax = fmax(amax, fabs(val));

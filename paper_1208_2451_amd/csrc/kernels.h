@@ -193,10 +193,68 @@ struct GemmArgs {
   const int32_t* c_rows;
   int gather_rows;            // gathered row indices are clamped into [0, gather_rows)
   const int32_t* a_rows;      // nullable: row i of A is A + a_rows[i] * lda (clamped too)
+  // With c_rows: 1 writes row r of C_new at C + c_rows[r] * ldc (C may then be
+  // C_in itself: each element is read and written by one thread).
+  int c_scatter;
 };
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t stream);
 hipError_t launch_gemm_batched(const GemmArgs* list, int count, int max_m, int max_n, int prec,
                                hipStream_t stream);
+
+// ------------------------------- block parallel / block pairwise LU_PRRP
+// After a tree level's strong RRQR (launch args `s`, which wrote each left-out
+// row's d_r into its panel columns): per node g, its left-out rows in node
+// order at elim + g * elim_stride, the records (node_sel[(node0 + g) kMaxB +
+// slot] = original row of the selected row, elim_node[original row] = node0
+// + g, *count = node0 + ngroups), and list[g] = the GEMM updating those rows'
+// trailing columns in place.
+struct BlockNodeArgs {
+  double* A;
+  int64_t lda, k0, n;
+  int m;                      // panel rows (n - k0)
+  int node0;                  // index of the level's first node within the panel
+  int32_t* elim;
+  int elim_stride;
+  const int64_t* perm;
+  int32_t* node_sel;          // this panel's [max nodes][kMaxB]
+  int32_t* elim_node;         // this panel's [n], by original row
+  int32_t* count;             // this panel's node count
+  GemmArgs* list;             // [ngroups]
+  double* amax;
+};
+hipError_t launch_block_nodes(const SrrqrArgs& s, const BlockNodeArgs& b, hipStream_t stream);
+// p[i] = v + step i
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, int32_t step, hipStream_t stream);
+
+// The caller's node records (final positions) from the ones kept by
+// original row: out = [panels, max_nodes, counts[panels],
+// sel[panels][max_nodes][b] (-1 where unused), elim[panels][n] (-1: not
+// eliminated in that panel)]; inv (n entries) is scratch.
+struct BlockRecordArgs {
+  const int64_t* perm;
+  int64_t n;
+  int panels, max_nodes, b;
+  const int32_t* counts;
+  const int32_t* node_sel;    // [panels][max_nodes][kMaxB]
+  const int32_t* elim_node;   // [panels][n]
+  int32_t* inv;
+  int32_t* out;
+};
+hipError_t launch_block_records(const BlockRecordArgs& a, hipStream_t stream);
+
+// One panel of the block factorization's forward sweep (Y in final row order).
+struct BlockForwardArgs {
+  const double* LU;
+  int64_t lda, n;
+  int b, j;
+  const int32_t* nodes;       // the records above
+  const double* ycur;
+  double* ynext;
+  int64_t ldy, nrhs;
+};
+hipError_t launch_block_forward(const BlockForwardArgs& a, hipStream_t stream);
+hipError_t launch_copy_rows(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                            int64_t nrhs, hipStream_t stream);
 
 // -------------------------------------------------------------- misc
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);

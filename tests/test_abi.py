@@ -186,3 +186,29 @@ def test_batch_plan_argument_errors(L):
     assert L.prrp_batch_plan_workspace_size(1, n8, b2, None, 96, ctypes.byref(need)) == -5
     assert L.prrp_batch_plan_run(None, None, 0) == -1
     assert L.prrp_batch_plan_destroy(None) == 0
+
+
+def test_block_factor_sizes_and_argument_errors(L):
+    ws = ctypes.c_size_t(0)
+    ne = ctypes.c_int64(0)
+    assert L.prrp_block_sizes(1024, 16, 0, 128, ctypes.byref(ws), ctypes.byref(ne)) == 0
+    P, MN = 1024 // 16, 2 * 8 - 1                  # 8 tiles of 128 rows: 15 binary-tree nodes
+    assert ne.value == 2 + P + P * MN * 16 + P * 1024
+    assert ws.value > _lib.workspace_size(1024, 16, 1, 128)
+    assert L.prrp_block_sizes(1024, 16, 1, 128, None, ctypes.byref(ne)) == 0
+    assert ne.value == 2 + P + P * 8 * 16 + P * 1024   # flat tree: one node per tile
+    assert L.prrp_block_sizes(1024, 16, 2, 128, None, None) == -3    # tree kind
+    assert L.prrp_block_sizes(1024, 16, 0, 16, None, None) == -4     # tile_rows <= b
+    f = L.prrp_block_factor
+    big = 1 << 40
+    assert f(None, 64, 64, 8, 2.0, 0, 32, 1, 1, big, 1, 1, big, None) == -1
+    assert f(1, 64, 64, 8, 1.0, 0, 32, 1, 1, big, 1, 1, big, None) == -5
+    assert f(1, 64, 64, 8, 2.0, 3, 32, 1, 1, big, 1, 1, big, None) == -6
+    assert f(1, 64, 64, 8, 2.0, 0, 8, 1, 1, big, 1, 1, big, None) == -7
+    assert f(1, 64, 64, 8, 2.0, 0, 32, 1, None, big, 1, 1, big, None) == -9
+    assert f(1, 64, 64, 8, 2.0, 0, 32, 1, 1, 10, 1, 1, big, None) == -10   # records too short
+    assert f(1, 64, 64, 8, 2.0, 0, 32, 1, 1, big, 1, 1, 16, None) == -13   # workspace too small
+    s = L.prrp_block_solve
+    assert s(1, 64, 64, 8, 1, None, 1, 1, 1, 1, 1, 1, big, None) == -6
+    assert s(1, 64, 64, 8, 1, 1, 1, 1, 1, 1, 0, 1, big, None) == -11
+    assert s(1, 64, 64, 8, 1, 1, 1, 1, 1, 1, 1, 1, 16, None) == -13
