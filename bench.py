@@ -283,6 +283,122 @@ def calu_sweep(n: int, b: int, tau: float, seed: int):
     return {"n": n, "b": b, "runs": out}
 
 
+def block_bench(n: int, b: int, tile_rows: int, tree: str, tau: float, seed: int, steps: int,
+                warmup: int):
+    """Block parallel (binary tree) or block pairwise (flat tree) LU_PRRP
+    (Section 5, Appendix E) on an N(0,1) matrix: factor time, TFLOP/s
+    (2n^3/3), growth, per-phase device times, and the solve's time and
+    backward error."""
+    import torch
+    import paper_1208_2451_amd as prrp
+    from paper_1208_2451_amd import _lib
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed + 7)
+    A0 = torch.randn(n, n, generator=g, dtype=torch.float64, device=dev)
+    A = torch.empty_like(A0)
+    ws_bytes, _ = _lib.block_sizes(n, b, _lib.TREES[tree], tile_rows)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        A.copy_(A0)
+        prrp.block_factor(A, b, tau, tree=tree, tile_rows=tile_rows, workspace=ws)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        A.copy_(A0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = prrp.block_factor(A, b, tau, tree=tree, tile_rows=tile_rows, workspace=ws)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    st = r.stats()
+    rhs = torch.randn(n, 1, generator=g, dtype=torch.float64, device=dev)
+    prrp.block_solve(A, r, rhs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = prrp.block_solve(A, r, rhs)
+    torch.cuda.synchronize()
+    solve_ms = 1e3 * (time.perf_counter() - t0)
+    res = (A0 @ x - rhs).abs().max().item()
+    eta = res / (A0.abs().max().item() * x.abs().max().item() * n)
+    _lib.profile_enable(True)
+    A.copy_(A0)
+    prrp.block_factor(A, b, tau, tree=tree, tile_rows=tile_rows, workspace=ws)
+    torch.cuda.synchronize()
+    phases = _lib.profile_read()
+    _lib.profile_enable(False)
+    ms = 1e3 * sum(times) / len(times)
+    ph = {k: v[0] for k, v in phases.items()}
+    kind = "block parallel" if tree == "binary" else "block pairwise"
+    out = {"workload": "%s LU_PRRP factor, n=%d, b=%d, tau=%g, %s tree over %d-row tiles, N(0,1) "
+                       "matrix" % (kind, n, b, tau, tree, tile_rows),
+           "ms_per_factor": ms, "tflops": 2.0 * n ** 3 / 3.0 / (ms * 1e-3) / 1e12, "steps": steps,
+           "g_W": st["g_W"], "max_abs_d": st["max_block_L"], "tree_height": st["tree_height"],
+           "info": st["info"], "swaps": st["swaps"], "solve_ms": solve_ms,
+           "backward_error": eta, "phase_ms_per_factor": ph,
+           "phase_launches_per_factor": {k: v[1] for k, v in phases.items()},
+           "roofline": {"kernel": "srrqr_kernel (tree nodes)", "bound": "alu",
+                        "ms_per_factor": ph["srrqr"],
+                        "note": "latency bound: every tree level is b dependent pivot steps, "
+                                "each followed by its nodes' updates"}}
+    del A, A0, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def block_sweep(tau: float, seed: int):
+    """Growth of block parallel LU_PRRP at n = 2048 with P = 16, 32 tiles and
+    b = 2, 4, 8, 16 (the setting of Figure "bluprrp"), and of block pairwise
+    LU_PRRP with the flat tree of height n / b (tiles of b rows) at n = 1024,
+    2048 and b = 8, 16, 32 (Figure "fluprrp"), on N(0,1) matrices.  The
+    figures are plots without printed values: the shape is what compares
+    (Section 5: block parallel growth rising with P, block pairwise growth
+    falling with b and staying below n)."""
+    import torch
+    import paper_1208_2451_amd as prrp
+    dev = torch.device("cuda:0")
+    out = {"parallel": [], "pairwise": []}
+
+    def one(n, b, tree, tile_rows):
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed + n + b)
+        A = torch.randn(n, n, generator=g, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = prrp.block_factor(A, b, tau, tree=tree, tile_rows=tile_rows)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        st = r.stats()
+        return {"n": n, "b": b, "tile_rows": tile_rows, "ms": ms, "g_W": st["g_W"],
+                "info": st["info"]}
+
+    for P in (16, 32):
+        for b in (2, 4, 8, 16):
+            row = one(2048, b, "binary", 2048 // P)
+            row["P"] = P
+            out["parallel"].append(row)
+    for n in (1024, 2048):
+        for b in (8, 16, 32):
+            row = one(n, b, "flat", b)
+            row["below_n"] = row["g_W"] < n
+            out["pairwise"].append(row)
+    torch.cuda.empty_cache()
+    return out
+
+
+def block_legs(tau: float, seed: int, steps: int, warmup: int):
+    """Block parallel at the CALU_PRRP workload (n = 16384, b = 128, 512-row
+    tiles), block pairwise at n = 8192 over 512-row tiles, and the growth sweep."""
+    steps = max(1, min(3, steps))
+    out = {"parallel": block_bench(16384, 128, 512, "binary", tau, seed, steps, warmup)}
+    log("block parallel", json.dumps(out["parallel"]))
+    out["pairwise"] = block_bench(8192, 128, 512, "flat", tau, seed, steps, warmup)
+    log("block pairwise", json.dumps(out["pairwise"]))
+    out["growth_sweep"] = block_sweep(tau, seed)
+    log("block growth sweep", json.dumps(out["growth_sweep"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +424,10 @@ def main():
                     help="order of the CALU_PRRP run (0 skips it)")
     ap.add_argument("--calu-only", action="store_true",
                     help="run only the CALU_PRRP leg (for kernel traces) and print its JSON")
+    ap.add_argument("--no-block", dest="block", action="store_false",
+                    help="skip the block parallel / block pairwise LU_PRRP legs")
+    ap.add_argument("--block-only", action="store_true",
+                    help="run only the block parallel / pairwise legs and print their JSON")
     ap.add_argument("--host-matrix", action="store_true",
                     help="build the kappa matrix with NumPy on the host (same recipe) and copy it "
                          "in, instead of building it with device QR")
@@ -329,6 +449,9 @@ def main():
     if args.calu_only:
         print(json.dumps(calu_bench(args.calu_n or 16384, 128, 512, args.tau, args.seed,
                                     args.steps, args.warmup)), flush=True)
+        return
+    if args.block_only:
+        print(json.dumps(block_legs(args.tau, args.seed, args.steps, args.warmup)), flush=True)
         return
 
     n, b, tau = args.n, args.b, args.tau
@@ -531,6 +654,11 @@ def main():
         calu["tile_sweep"] = calu_sweep(8192, 128, tau, args.seed)
         log("calu tile sweep", json.dumps(calu["tile_sweep"]))
 
+    block = None
+    if args.block:
+        log("block parallel / pairwise LU_PRRP")
+        block = block_legs(tau, args.seed, args.steps, 1)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d panels" % args.cpu_panels)
@@ -553,6 +681,7 @@ def main():
         "solves": solves,
         "serving": serving_out,
         "calu_prrp": calu,
+        "block_lu_prrp": block,
     }
     print(json.dumps(out), flush=True)
 

@@ -128,7 +128,8 @@ int calu_prrp_factor(double* A, int64_t n, int64_t lda, int b, double tau, int t
 
 /* Block parallel (tree PRRP_TREE_BINARY) and block pairwise (PRRP_TREE_FLAT)
  * LU_PRRP (Section 5, Appendix E).  Each panel's active rows are cut into
- * tiles as in calu_prrp_factor; at every node of the reduction tree strong
+ * tiles as in calu_prrp_factor, except that tile_rows may equal b (the
+ * pairwise tree of height n / b: a b-row leaf keeps its rows); at every node of the reduction tree strong
  * RRQR of the node's rows selects b of them and every other row r of the node
  * is eliminated against them at once: with d_r its row of
  * (R11^-1 R12)^T, row r's columns right of the panel become

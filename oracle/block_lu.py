@@ -32,7 +32,10 @@ lists panel j's nodes in execution order (leaves first, up to the root) as
 (selected rows, eliminated rows), both as original row numbers, the selected
 ones in slot order (the order of d_r's entries).
 
-Readings (shared with CALU_PRRP in ``lu``): tiles follow ``lu.tile_bounds``;
+Readings (shared with CALU_PRRP in ``lu``): tiles follow ``lu.tile_bounds``
+except that a tile may hold exactly b rows (the block pairwise tree of
+height n / b that Section 5 describes stacks the running b rows over b new
+ones; a b-row leaf keeps all its rows);
 stacking orders and the odd-node promotion follow ``lu.tournament``; a node
 of a rank-deficient panel takes its multipliers from ``lu._qr_ratio`` (the
 paper leaves that case open).  The growth recorded is the largest magnitude
@@ -51,8 +54,21 @@ from dataclasses import dataclass, field
 import numpy as np
 from scipy.linalg import solve_triangular
 
-from .lu import _qr_ratio, _swap_rows, gepp_inplace, tile_bounds
+from .lu import _qr_ratio, _swap_rows, gepp_inplace
 from .srrqr import strong_rrqr
+
+
+def tile_bounds(m: int, tile_rows: int, b: int):
+    """Top-down row tiles of ``tile_rows`` (>= b) rows; a last remainder of
+    fewer than b + 1 rows joins its predecessor."""
+    if tile_rows < b:
+        raise ValueError("tile_rows must be at least b")
+    starts = list(range(0, m, tile_rows))
+    bounds = [[s, min(s + tile_rows, m)] for s in starts]
+    if len(bounds) > 1 and bounds[-1][1] - bounds[-1][0] <= b:
+        bounds[-2][1] = bounds[-1][1]
+        bounds.pop()
+    return [tuple(x) for x in bounds]
 
 
 @dataclass

@@ -2101,7 +2101,7 @@ int prrp_block_sizes(int64_t n, int b, int tree, int64_t tile_rows, size_t* ws_b
   if (n < 1 || n > kMaxN) return -1;
   if (b < 1 || b > kMaxB || b > n) return -2;
   if (tree != PRRP_TREE_BINARY && tree != PRRP_TREE_FLAT) return -3;
-  if (tile_rows < b + 1) return -4;
+  if (tile_rows < b) return -4;
   if ((n + tile_rows - 1) / tile_rows > kMaxGroups) return -4;
   if (ws_bytes) *ws_bytes = make_block_layout(n, b, tree, tile_rows).total;
   if (node_entries) *node_entries = block_nodes_len(n, b, tree, tile_rows);
@@ -2117,7 +2117,7 @@ int prrp_block_factor(double* A, int64_t n, int64_t lda, int b, double tau, int 
   if (b < 1 || b > kMaxB || b > n) return -4;
   if (!(tau > 1.0) || !std::isfinite(tau)) return -5;
   if (tree != PRRP_TREE_BINARY && tree != PRRP_TREE_FLAT) return -6;
-  if (tile_rows < b + 1 || (n + tile_rows - 1) / tile_rows > kMaxGroups) return -7;
+  if (tile_rows < b || (n + tile_rows - 1) / tile_rows > kMaxGroups) return -7;
   if (!perm) return -8;
   if (!nodes) return -9;
   if (node_entries < block_nodes_len(n, b, tree, tile_rows)) return -10;

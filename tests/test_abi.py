@@ -198,13 +198,14 @@ def test_block_factor_sizes_and_argument_errors(L):
     assert L.prrp_block_sizes(1024, 16, 1, 128, None, ctypes.byref(ne)) == 0
     assert ne.value == 2 + P + P * 8 * 16 + P * 1024   # flat tree: one node per tile
     assert L.prrp_block_sizes(1024, 16, 2, 128, None, None) == -3    # tree kind
-    assert L.prrp_block_sizes(1024, 16, 0, 16, None, None) == -4     # tile_rows <= b
+    assert L.prrp_block_sizes(1024, 16, 0, 15, None, None) == -4     # tile_rows < b
+    assert L.prrp_block_sizes(1024, 16, 1, 16, None, None) == 0      # b-row tiles (pairwise)
     f = L.prrp_block_factor
     big = 1 << 40
     assert f(None, 64, 64, 8, 2.0, 0, 32, 1, 1, big, 1, 1, big, None) == -1
     assert f(1, 64, 64, 8, 1.0, 0, 32, 1, 1, big, 1, 1, big, None) == -5
     assert f(1, 64, 64, 8, 2.0, 3, 32, 1, 1, big, 1, 1, big, None) == -6
-    assert f(1, 64, 64, 8, 2.0, 0, 8, 1, 1, big, 1, 1, big, None) == -7
+    assert f(1, 64, 64, 8, 2.0, 0, 7, 1, 1, big, 1, 1, big, None) == -7
     assert f(1, 64, 64, 8, 2.0, 0, 32, 1, None, big, 1, 1, big, None) == -9
     assert f(1, 64, 64, 8, 2.0, 0, 32, 1, 1, 10, 1, 1, big, None) == -10   # records too short
     assert f(1, 64, 64, 8, 2.0, 0, 32, 1, 1, big, 1, 1, 16, None) == -13   # workspace too small

@@ -145,6 +145,14 @@ def test_block_random(tree, n, b, tr):
     _compare(A, b, 2.0, tree, tr, tag="randn")
 
 
+@pytest.mark.parametrize("n,b", [(256, 16), (130, 8)])
+def test_block_pairwise_height_n_over_b(n, b):
+    # the block pairwise tree of height n / b (tiles of b rows)
+    A, _ = inputs.randn_system(n, 5 * n + b)
+    st, f = _compare(A, b, 2.0, "flat", b, tag="tiles of b rows")
+    assert f.tree_height == (n + b - 1) // b - 2 or f.tree_height == n // b - 2
+
+
 @pytest.mark.parametrize("tree", ["binary", "flat"])
 def test_block_forced_exchanges(tree):
     A, _ = inputs.randn_system(160, 13)

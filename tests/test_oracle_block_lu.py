@@ -76,8 +76,10 @@ def _exact_b1(A, tile_rows, tree):
 
 
 @pytest.mark.parametrize("tree", ["binary", "flat"])
-@pytest.mark.parametrize("n,tile_rows,seed", [(9, 2, 1), (12, 3, 2), (11, 4, 3)])
+@pytest.mark.parametrize("n,tile_rows,seed", [(9, 2, 1), (12, 3, 2), (11, 4, 3), (10, 1, 4)])
 def test_b1_is_parallel_or_pairwise_pivoting_exactly(tree, n, tile_rows, seed):
+    # tile_rows = 1 with the flat tree is Sorensen's pairwise pivoting: the
+    # running pivot row meets each next row in turn
     A = _distinct_int_matrix(n, seed)
     M, perm = _exact_b1(A, tile_rows, tree)
     f = ob.block_lu_prrp(A, 1, 2.0, tile_rows, tree)
