@@ -123,24 +123,25 @@ int groups_for_rows(int64_t rows, int cap, int target, int bw) {
 }
 
 // Compute units that one strong-RRQR tile of G workgroups (bw columns, rpw
-// rows each) occupies when all of them are resident, or -1 if the occupancy
-// query fails.  Every workgroup of a tile waits on the others, so the tile
-// must fit at once.
-int64_t tile_cus(int G, int bw, int rpw, int bpc_given = 0) {
-  if (bpc_given > 0) return (G + bpc_given - 1) / bpc_given;
+// rows each) occupies when all of them are resident -- or `total` workgroups
+// of such tiles, when given -- or -1 if the occupancy query fails.  Every
+// workgroup of a tile waits on the others, so the tile must fit at once.
+int64_t tile_cus(int G, int bw, int rpw, int bpc_given = 0, int64_t total = 0) {
+  const int64_t wgs = total > 0 ? total : G;
+  if (bpc_given > 0) return (wgs + bpc_given - 1) / bpc_given;
   static std::mutex mu;
-  static std::vector<std::pair<int64_t, int>> cache;   // ((bw << 32) | rpw, blocks)
-  const int64_t key = ((int64_t)bw << 32) | (uint32_t)rpw;
+  static std::vector<std::pair<int64_t, int>> cache;   // ((bw, rpw, G <= 16), blocks)
+  const int64_t key = ((int64_t)bw << 32) | ((int64_t)(G <= 16) << 31) | (uint32_t)rpw;
   int bpc = 0;
   {
     std::lock_guard<std::mutex> g(mu);
     for (auto& kv : cache) if (kv.first == key) bpc = kv.second;
     if (bpc == 0) {
-      if (srrqr_blocks_per_cu(bw, rpw, &bpc) != hipSuccess || bpc < 1) return -1;
+      if (srrqr_blocks_per_cu(bw, rpw, G, &bpc) != hipSuccess || bpc < 1) return -1;
       cache.push_back({key, bpc});
     }
   }
-  return (G + bpc - 1) / bpc;
+  return (wgs + bpc - 1) / bpc;
 }
 
 struct Layout {
@@ -432,7 +433,7 @@ struct Ctx {
     a.tau_bits = tau_bits(tau);
     // tiles interleaved over the XCDs when the whole launch fits the device
     if (a.ngroups > 1 && a.G > 1 && interleave_tiles()) {
-      const int64_t cus = tile_cus(a.ngroups * a.G, a.bw, a.rpw);
+      const int64_t cus = tile_cus(a.G, a.bw, a.rpw, 0, (int64_t)a.ngroups * a.G);
       a.interleave = (cus > 0 && cus <= device_cus()) ? 1 : 0;
     }
     hipError_t e;

@@ -82,9 +82,10 @@ size_t srrqr_smem_bytes(int bw, int nt);
 // with 1024 threads).
 int srrqr_max_rpw();
 hipError_t srrqr_prepare();   // raise the dynamic LDS limit of every instance
-// Workgroups of the instance for (bw, rows per workgroup) one CU holds at once
-// (after srrqr_prepare).  Every workgroup of a tile must be resident together.
-hipError_t srrqr_blocks_per_cu(int bw, int rpw, int* blocks);
+// Workgroups of the instance for (bw, rows per workgroup, workgroups per
+// tile) one CU holds at once (after srrqr_prepare).  Every workgroup of a
+// tile must be resident together.
+hipError_t srrqr_blocks_per_cu(int bw, int rpw, int G, int* blocks);
 
 // ----------------------------------------------- diagonal block and moves
 struct GeppArgs {

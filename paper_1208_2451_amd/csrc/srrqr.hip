@@ -753,9 +753,11 @@ void srrqr_kernel(SrrqrArgs a) {
 // workgroup size (1024 threads once a workgroup holds more than 128 rows)
 // and rows per thread.
 struct Shape { int cpt, nt, rpt; };
-// A workgroup of at most 64 rows runs with 512 threads (one row per thread,
-// two waves per SIMD, which hide each other's latencies), one of 65..128
-// rows with 256; PRRP_SRRQR_THREADS=256 or 512 fixes the size for those.
+// A workgroup of at most 64 rows in a tile of at most 16 workgroups runs
+// with 512 threads (one row per thread, two waves per SIMD; measured faster
+// on CALU_PRRP's tree nodes), any other of at most 128 rows with 256 (faster
+// for a panel spread over 64 workgroups, where the exchange dominates);
+// PRRP_SRRQR_THREADS=256 or 512 fixes the size for those.
 int mid_threads() {
   static int nt = -1;
   if (nt < 0) {
@@ -765,11 +767,11 @@ int mid_threads() {
   }
   return nt;
 }
-Shape srrqr_shape(int bw, int rpw) {
+Shape srrqr_shape(int bw, int rpw, int G) {
   int cpt = (bw + 7) / 8;
   cpt = cpt <= 2 ? (cpt <= 1 ? 1 : 2) : (cpt <= 4 ? 4 : (cpt <= 8 ? 8 : 16));
   int nt = mid_threads();
-  if (nt == 0) nt = rpw <= kThreadsMid / 8 ? kThreadsMid : kThreads;
+  if (nt == 0) nt = (rpw <= kThreadsMid / 8 && G <= 16) ? kThreadsMid : kThreads;
   if (rpw > (kThreads / 8) * 4) nt = kThreadsWide;
   return {cpt, nt, (rpw + nt / 8 - 1) / (nt / 8)};
 }
@@ -793,7 +795,7 @@ Shape srrqr_shape(int bw, int rpw) {
   }
 
 hipError_t launch_srrqr(const SrrqrArgs& a, hipStream_t stream) {
-  const Shape sh = srrqr_shape(a.bw, a.rpw);
+  const Shape sh = srrqr_shape(a.bw, a.rpw, a.G);
   const size_t smem = srrqr_smem_bytes(a.bw, sh.nt);
   PRRP_SRRQR_SHAPES(PRRP_SRRQR_CASE)
   return hipErrorInvalidValue;
@@ -806,8 +808,8 @@ int srrqr_max_rpw() { return kRowsWide; }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, srrqr_kernel<C, R, T>, T, smem);
 
 // Workgroups of one instance that a compute unit holds at once.
-hipError_t srrqr_blocks_per_cu(int bw, int rpw, int* blocks) {
-  const Shape sh = srrqr_shape(bw, rpw);
+hipError_t srrqr_blocks_per_cu(int bw, int rpw, int G, int* blocks) {
+  const Shape sh = srrqr_shape(bw, rpw, G);
   const size_t smem = srrqr_smem_bytes(bw, sh.nt);
   PRRP_SRRQR_SHAPES(PRRP_SRRQR_OCC)
   return hipErrorInvalidValue;
