@@ -89,13 +89,37 @@ __device__ __forceinline__ void trsv_body(const double* LU, int64_t n, int64_t l
       const int i = (tid >> 6) + 4 * u, c = tid & 63;
       v[u] = (i < rows && c < rows) ? LU[(r0 + i) * lda + r0 + c] : 0.0;
     }
+    // stored as the substitution uses it: only the entries that act on other
+    // rows' values (strictly below the diagonal for L, strictly above for
+    // U), so that a step is one FMA on every lane; the diagonal itself in the
+    // padding column
 #pragma unroll
-    for (int u = 0; u < 16; ++u) D[(tid >> 6) + 4 * u][tid & 63] = v[u];
+    for (int u = 0; u < 16; ++u) {
+      const int i = (tid >> 6) + 4 * u, c = tid & 63;
+      D[i][c] = (LOWER ? i > c : i < c) ? v[u] : 0.0;
+      if (i == c) D[i][NB] = v[u];
+    }
   }
+  __syncthreads();
   const int ri = tid & 63, q = tid >> 6;      // row, column quarter
   const int nd = LOWER ? k : nb - 1 - k;      // blocks this one depends on
+  // What the diagonal solve needs besides the solution values, loaded before
+  // the wait for them: this lane's row of the block (in registers), its
+  // right-hand sides, and (upper) the reciprocal of its diagonal entry.
+  double drow[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) drow[i] = D[lane][i];
+  const double dself = (lane < rows) ? D[lane][NB] : 1.0;
+  const double rinv = 1.0 / dself;
+  constexpr int RPW = (RCT + 3) / 4;          // right-hand sides per wave and pass
   for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RCT) {
     const int nr = (int)min<int64_t>(RCT, nrhs - rc0);
+    double bin[RPW];
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+      const int r = wave + 4 * t;
+      bin[t] = (r < nr && lane < rows) ? Bin[(r0 + lane) * ldb + rc0 + r] : 0.0;
+    }
     double acc[RCT];
 #pragma unroll
     for (int r = 0; r < RCT; ++r) acc[r] = 0.0;
@@ -142,38 +166,34 @@ __device__ __forceinline__ void trsv_body(const double* LU, int64_t n, int64_t l
     __syncthreads();
     // One wave per right-hand side solves the diagonal block.  Each lane keeps
     // its row of the block in registers and takes the solved values by
-    // readlane, so a substitution step is one FMA and one lane read.
-    for (int r = wave; r < nr; r += 4) {
-      double drow[NB];
+    // readlane, so a substitution step is one lane read and one FMA (the
+    // row holds zeros where it must not act).
 #pragma unroll
-      for (int i = 0; i < NB; ++i) drow[i] = D[lane][i];
+    for (int t = 0; t < RPW; ++t) {
+      const int r = wave + 4 * t;
+      if (r >= nr) break;
       double bv = 0.0;
       if (lane < rows)
-        bv = Bin[(r0 + lane) * ldb + rc0 + r] -
-             (part[0][lane][r] + part[1][lane][r] + part[2][lane][r] + part[3][lane][r]);
+        bv = bin[t] - (part[0][lane][r] + part[1][lane][r] + part[2][lane][r] + part[3][lane][r]);
       if (LOWER) {
         // rows past the block's end hold zeros, so their steps change nothing
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          const double y = readlane_d(bv, i);
-          const double upd = fma(-drow[i], y, bv);
-          bv = (lane > i) ? upd : bv;
-        }
+        for (int i = 0; i < NB; ++i) bv = fma(-drow[i], readlane_d(bv, i), bv);
       } else {
         // quotient b_i / u_ii from the reciprocal and one exact-remainder
-        // correction (the remainder b - u y is exact under FMA), computed
-        // while the chain runs
-        const double dself = (lane < rows) ? D[lane][lane] : 1.0;
-        const double rinv = 1.0 / dself;
+        // correction (the remainder b - u y is exact under FMA).  Lane i keeps
+        // b_i minus the later rows' terms; its quotient is formed for the
+        // substitution and again, identically, for every lane at the end
 #pragma unroll
         for (int i = NB - 1; i >= 0; --i) {
           const double bi = readlane_d(bv, i);
           const double di = readlane_d(dself, i), rr = readlane_d(rinv, i);
           double y = bi * rr;
           y = fma(rr, fma(-di, y, bi), y);
-          const double upd = fma(-drow[i], y, bv);
-          bv = (lane < i) ? upd : ((lane == i) ? y : bv);
+          bv = fma(-drow[i], y, bv);
         }
+        const double y = bv * rinv;
+        bv = fma(rinv, fma(-dself, y, bv), y);
       }
       if (lane < rows)
         st_dev(reinterpret_cast<uint64_t*>(Yout + (r0 + lane) * ld + rc0 + r),
