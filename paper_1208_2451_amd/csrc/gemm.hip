@@ -17,7 +17,14 @@
 // list (the selected rows, before the moves of Pi_j) and rows of C_in through
 // another (the rows that land at each position), writing C out of place.
 // The CALU_PRRP root gathers the rows of A (the panel rows that land at each
-// position) for Y = A21 A11^-1.
+// position) for Y = A21 A11^-1.  B's row indices are staged in LDS once per
+// workgroup (K <= 256), so no K-slab waits for an index load.
+//
+// The epilogue issues its loads in groups: all output-row indices, then per
+// 16-row block all input values, all results, all stores.  On gfx950 the
+// vector-memory counter covers stores as well as loads, so a wait for a load
+// issued after a store also waits for the store; one output at a time (load,
+// wait, store) cost two memory latencies per output.
 //
 // MFMA 16x16 operand layout (wave64): A operand lane l holds A[l%16][k-group
 // l/16], B operand lane l holds B[k-group l/16][l%16].  The 4 accumulator
@@ -69,6 +76,11 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int bx, int by) {
   __shared__ T As[2][KS][BM + APAD];
   __shared__ T Bs[2][KS][BN + APAD];
   __shared__ double red[WM * WN];
+  // the gathered B rows' indices, staged once (a per-slab index load would
+  // put a dependent load latency, and a wait for every load in flight, into
+  // each K-slab)
+  constexpr int kSelK = 256;
+  __shared__ int bsel[kSelK];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -89,23 +101,30 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int bx, int by) {
   const int64_t arow =
       (gr < M) ? (g.a_rows ? (int64_t)min(max(g.a_rows[gr], 0), g.gather_rows - 1) : (int64_t)gr)
                : 0;
-  auto load_slab = [&](int k0) {
+  const bool bsel_lds = g.b_rows != nullptr && K <= kSelK;
+  if (bsel_lds) {
+    for (int k = tid; k < K; k += NT) bsel[k] = min(max(g.b_rows[k], 0), g.gather_rows - 1);
+  }
+  __syncthreads();
+  auto load_slab = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int gk = k0 + a_k + v;
       ra[v] = (gr < M && gk < K) ? g.A[arow * g.lda + gk] : 0.0;
     }
     const int gk = k0 + b_k;
-    const int64_t brow =
-        (gk < K) ? (g.b_rows ? (int64_t)min(max(g.b_rows[gk], 0), g.gather_rows - 1) : (int64_t)gk)
-                 : 0;
+    int64_t brow = 0;
+    if (gk < K) {
+      if (bsel_lds) brow = bsel[gk];
+      else brow = g.b_rows ? (int64_t)min(max(g.b_rows[gk], 0), g.gather_rows - 1) : (int64_t)gk;
+    }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
       const int gc = n0 + b_n + v;
       rb[v] = (gk < K && gc < N) ? g.B[brow * g.ldb + gc] : 0.0;
     }
   };
-  auto store_slab = [&](int buf) {
+  auto store_slab = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int v = 0; v < AV; ++v) As[buf][a_k + v][a_row] = conv<T>(ra[v]);
 #pragma unroll
@@ -123,13 +142,8 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int bx, int by) {
     }
 
   const int nslab = (K + KS - 1) / KS;
-  load_slab(0);
-  store_slab(0);
-  __syncthreads();
   const int li = lane & 15, lk = lane >> 4;
-  for (int sl = 0; sl < nslab; ++sl) {
-    const int cur = sl & 1;
-    if (sl + 1 < nslab) load_slab((sl + 1) * KS);
+  auto compute = [&](int cur) __attribute__((always_inline)) {
     if constexpr (sizeof(T) == 8) {
 #pragma unroll
       for (int kq = 0; kq < KS / 4; ++kq) {
@@ -179,32 +193,84 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int bx, int by) {
         for (int j = 0; j < WJ; ++j)
           accf[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], accf[i][j], 0, 0, 0);
     }
-    if (sl + 1 < nslab) {
-      store_slab(cur ^ 1);
-    }
+  };
+  load_slab(0);
+  store_slab(0);
+  __syncthreads();
+  for (int sl = 0; sl < nslab; ++sl) {
+    const int cur = sl & 1;
+    if (sl + 1 < nslab) load_slab((sl + 1) * KS);
+    compute(cur);
+    if (sl + 1 < nslab) store_slab(cur ^ 1);
     __syncthreads();
   }
 
-  // epilogue
-  double amax = 0.0;
+  // epilogue, in passes so that the loads of a pass are all in flight
+  // together (a load, its wait and a store per output would serialize them,
+  // since C may alias Cin): first the output rows' indices.  Every output
+  // element is a distinct memory element read and written by this thread
+  // only.
+  constexpr int RV = 4;                 // output rows per 16 x 16 block and lane
+  int craw[WI][RV];
 #pragma unroll
   for (int i = 0; i < WI; ++i)
 #pragma unroll
+    for (int v = 0; v < RV; ++v) {
+      const int r = m0 + wm * (BM / WM) + i * 16 + ((sizeof(T) == 8) ? (lk + 4 * v) : (4 * lk + v));
+      // (rows past M read a valid index and are not used; no divergent branch
+      // around the loads)
+      craw[i][v] = g.Cin ? g.c_rows[min(r, M - 1)] : r;
+    }
+  // all index loads issued before the first use (the scheduler would
+  // otherwise wait for each right after it)
+  __builtin_amdgcn_sched_barrier(0);
+  int64_t crow[WI][RV];
+#pragma unroll
+  for (int i = 0; i < WI; ++i)
+#pragma unroll
+    for (int v = 0; v < RV; ++v)
+      crow[i][v] = g.Cin ? (int64_t)min(max(craw[i][v], 0), g.gather_rows - 1) : (int64_t)craw[i][v];
+  // then, one 16-row block at a time (so that the input values held at once
+  // stay few), the input values and the stores
+  double amax = 0.0;
+#pragma unroll
+  for (int i = 0; i < WI; ++i) {
+    double cinv[WJ][RV];
+#pragma unroll
     for (int j = 0; j < WJ; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
+      for (int v = 0; v < RV; ++v) {
         const int r = m0 + wm * (BM / WM) + i * 16 + ((sizeof(T) == 8) ? (lk + 4 * v) : (4 * lk + v));
         const int c = n0 + wn * (BN / WN) + j * 16 + li;
-        if (r < M && c < N) {
-          const double p = (sizeof(T) == 8) ? accd[i][j][v] : (double)accf[i][j][v];
-          const int64_t gcr = g.Cin ? (int64_t)min(max(g.c_rows[r], 0), g.gather_rows - 1) : r;
-          double* cp = g.C + (g.c_scatter ? gcr : (int64_t)r) * g.ldc + c;
-          const double* cin = g.Cin ? g.Cin + gcr * g.ldcin + c : cp;
-          const double val = (g.beta != 0.0) ? fma(g.alpha, p, g.beta * *cin) : g.alpha * p;
-          *cp = val;
-          amax = fmax(amax, fabs(val));
-        }
+        const double* cin = g.Cin ? g.Cin + crow[i][v] * g.ldcin + c
+                                  : g.C + (g.c_scatter ? crow[i][v] : (int64_t)r) * g.ldc + c;
+        cinv[j][v] = (r < M && c < N && g.beta != 0.0) ? *cin : 0.0;
       }
+    // every value of the block formed before its first store: a wait for a
+    // load while a store is pending must wait for the store too
+    __builtin_amdgcn_sched_barrier(0);
+    // (the maximum is taken here, unconditionally, so that the values are
+    // not moved into the stores' branches)
+#pragma unroll
+    for (int j = 0; j < WJ; ++j)
+#pragma unroll
+      for (int v = 0; v < RV; ++v) {
+        const int r = m0 + wm * (BM / WM) + i * 16 + ((sizeof(T) == 8) ? (lk + 4 * v) : (4 * lk + v));
+        const int c = n0 + wn * (BN / WN) + j * 16 + li;
+        const double p = (sizeof(T) == 8) ? accd[i][j][v] : (double)accf[i][j][v];
+        cinv[j][v] = (g.beta != 0.0) ? fma(g.alpha, p, g.beta * cinv[j][v]) : g.alpha * p;
+        amax = fmax(amax, (r < M && c < N) ? fabs(cinv[j][v]) : 0.0);
+      }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < WJ; ++j)
+#pragma unroll
+      for (int v = 0; v < RV; ++v) {
+        const int r = m0 + wm * (BM / WM) + i * 16 + ((sizeof(T) == 8) ? (lk + 4 * v) : (4 * lk + v));
+        const int c = n0 + wn * (BN / WN) + j * 16 + li;
+        if (r < M && c < N) g.C[(g.c_scatter ? crow[i][v] : (int64_t)r) * g.ldc + c] = cinv[j][v];
+      }
+  }
   if (g.amax) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
