@@ -268,19 +268,51 @@ __device__ __forceinline__ void residual_body(const double* A, int64_t n, int64_
       s[r] = 0.0;
       den[r] = fabs(p[r]);
     }
-    for (int64_t c = lane; c < n; c += 64) {
-      const double a = arow[c];
+    if (nr == 1) {
+      // one right-hand side: eight columns' loads in flight per lane ahead of
+      // their (unchanged, sequential) Dot2 steps; one load at a time left the
+      // kernel latency-bound at about a third of the HBM rate
+      double p0 = p[0], s0 = s[0], d0 = den[0];
+      const double* xc = X + rc0;
+      auto step = [&](double a, double x) __attribute__((always_inline)) {
+        const double h = a * x;
+        const double e = fma(a, x, -h);
+        double t, q;
+        two_sum(p0, -h, t, q);
+        p0 = t;
+        s0 += q - e;
+        if (wout) d0 = fma(fabs(a), fabs(x), d0);
+      };
+      int64_t c = lane;
+      for (; c + 64 * 7 < n; c += 64 * 8) {
+        double av[8], xv[8];
 #pragma unroll
-      for (int r = 0; r < RC; ++r) {
-        if (r < nr) {
-          const double x = X[c * ldx + rc0 + r];
-          const double h = a * x;
-          const double e = fma(a, x, -h);
-          double t, q;
-          two_sum(p[r], -h, t, q);
-          p[r] = t;
-          s[r] += q - e;
-          if (wout) den[r] = fma(fabs(a), fabs(x), den[r]);
+        for (int u = 0; u < 8; ++u) {
+          av[u] = arow[c + 64 * u];
+          xv[u] = xc[(c + 64 * u) * ldx];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) step(av[u], xv[u]);
+      }
+      for (; c < n; c += 64) step(arow[c], xc[c * ldx]);
+      p[0] = p0;
+      s[0] = s0;
+      den[0] = d0;
+    } else {
+      for (int64_t c = lane; c < n; c += 64) {
+        const double a = arow[c];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+          if (r < nr) {
+            const double x = X[c * ldx + rc0 + r];
+            const double h = a * x;
+            const double e = fma(a, x, -h);
+            double t, q;
+            two_sum(p[r], -h, t, q);
+            p[r] = t;
+            s[r] += q - e;
+            if (wout) den[r] = fma(fabs(a), fabs(x), den[r]);
+          }
         }
       }
     }
