@@ -431,10 +431,17 @@ struct Ctx {
     a.stats = stats;
     a.abort_flag = abort_flag();
     a.tau_bits = tau_bits(tau);
-    // tiles interleaved over the XCDs when the whole launch fits the device
+    // Tiles interleaved over the XCDs when the whole launch fits the CUs it
+    // can count on: the device, or while far updates run on the side stream
+    // the CUs reserved from them.  A launch that only partly fits, with its
+    // tiles interleaved, holds some workgroups of every tile resident and
+    // no tile can finish until the far update does (measured: 12 ms at an
+    // early panel of CALU_PRRP at n = 16384); in tile order the resident
+    // tiles finish and free their CUs for the rest.
     if (a.ngroups > 1 && a.G > 1 && interleave_tiles()) {
       const int64_t cus = tile_cus(a.G, a.bw, a.rpw, 0, (int64_t)a.ngroups * a.G);
-      a.interleave = (cus > 0 && cus <= device_cus()) ? 1 : 0;
+      const int64_t room = (side != nullptr && g_side.main_cus > 0) ? g_side.main_cus : device_cus();
+      a.interleave = (cus > 0 && cus <= room) ? 1 : 0;
     }
     hipError_t e;
     {
