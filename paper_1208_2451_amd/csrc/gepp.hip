@@ -349,120 +349,210 @@ hipError_t launch_root_prep(const GeppArgs& a, const int32_t* winners, int32_t* 
 // S[i][j] = (A11^-1)[q_i][p_j], q the inverse of p.  An exactly zero pivot
 // sets info (the column).
 //
-// The steps run in blocks of 8 with the column inside the block unrolled, so
-// every register index is static.  One step:
-//  (1) the owners of column k (tx == k / 8) post its entries and their rows'
-//      keys, then clear their column-k entries;
-//  (2) after a barrier every thread takes the winning row p; the 16 threads
-//      holding row p post it scaled by 1 / pivot (with 1 / pivot in column
-//      k), clear their copy and post -1 as its column-k entry;
-//  (3) after a second barrier every entry takes S -= f_i r_c, f_i the posted
-//      column-k entry of its row and r the posted row: rows i != p get the
-//      elimination (column k: -f_i / pivot), row p becomes the scaled row.
+// Blocked by 8 columns (the same pivots and the same result up to rounding
+// order as one column at a time):
+//  (1) the owners of the block's columns post them to LDS (all rows);
+//  (2) wave 0 runs the block's 8 steps on those columns alone, in registers
+//      with no barrier and no branch (lane l holds rows l and l + 64): a row
+//      i != p takes v -= g_i r with g_i = v_ik / pivot and r the pivot row, so
+//      the reciprocal feeds the FMAs directly; the block's columns then hold
+//      T, the columns p_k of the block's accumulated transform;
+//  (3) the holders of the block's pivot rows post those rows as they were
+//      before the block;
+//  (4) every other column takes S[i][j] = [i not a pivot row of the block]
+//      S[i][j] + sum_k T[i][k] S_old[p_k][j], a rank-8 update, and the
+//      block's columns take T.
+// Three barriers per 8 columns; the LDS buffers alternate between blocks.
+// A last block of fewer than 8 columns runs its surplus steps as no-ops:
+// every row is used by then, so the winning key is 0 and the reciprocal 0.
 constexpr int kInvThreads = 256;
 
 __global__ __launch_bounds__(kInvThreads) void block_inverse_kernel(GeppArgs a, double* W) {
-  __shared__ double colk[2][kMaxB];
-  __shared__ double rowp[2][kMaxB];
-  __shared__ uint64_t wkeys[2][kInvThreads / 64];
-  __shared__ int pivrow[kMaxB];     // p_k
-  __shared__ int slotof[kMaxB];     // q: the step whose pivot row is i
+  // lbuf: pan[2] (block columns: column c, row i at c kMaxB + i), then
+  // prw[2] (old pivot rows: step kc, column j at kc kMaxB + j); at the end
+  // the staging of 32 rows of W
+  __shared__ double lbuf[4 * 8 * kMaxB];
+  __shared__ int pivrow[kMaxB];           // p_k
+  __shared__ int slotof[kMaxB];           // q: the step whose pivot row is i (-1: none yet)
   const int bw = a.bw;
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
   const int wave = tid >> 6;
-  // T[c][r] = entry (8 ty + r, 8 tx + c): one 8-entry array per column, so
-  // that the pivot row's uniform index selects registers directly
+  const int lane = tid & 63;
+  // T[c][r] = entry (8 ty + r, 8 tx + c); the row indices are loaded first
   typedef double col8 __attribute__((ext_vector_type(8)));
   col8 T[8];
-  unsigned usedm = 0;                                   // bit r: row 8 ty + r is used
+  // (every load in bounds and unconditional, so that all of them are in
+  // flight together; padding entries are replaced by 0 afterwards)
+  int srow[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) srow[r] = a.sel[min(8 * ty + r, bw - 1)];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const int i = 8 * ty + r;
-    if (i >= bw) usedm |= 1u << r;                      // padding rows never pivot
-    const int64_t sr = i < bw ? min(max(a.sel[i], 0), a.m - 1) : 0;
+    const int64_t sr = min(max(srow[r], 0), a.m - 1);
     const double* src = a.panel ? a.panel + sr * a.ldp : a.A + (a.k0 + sr) * a.lda + a.k0;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int j = 8 * tx + c;
-      T[c][r] = (i < bw && j < bw) ? src[j] : 0.0;
-    }
+    for (int c = 0; c < 8; ++c) T[c][r] = src[min(8 * tx + c, bw - 1)];
   }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) T[c][r] = (8 * ty + r < bw && 8 * tx + c < bw) ? T[c][r] : 0.0;
+  if (tid < kMaxB) slotof[tid] = -1;
+  // the pivot rows of surplus steps are never posted: keep their terms finite
+  for (int e = tid; e < 2 * 8 * kMaxB; e += kInvThreads) lbuf[2 * 8 * kMaxB + e] = 0.0;
+  // wave 0's rows lane and lane + 64 (padding rows never pivot)
+  bool used0 = lane >= bw, used1 = lane + 64 >= bw;
   const int nkt = (bw + 7) >> 3;
   for (int kt = 0; kt < nkt; ++kt) {
+    const int buf = kt & 1;
+    const int nk = min(8, bw - 8 * kt);          // steps in this block
+    double* const pan = lbuf + buf * 8 * kMaxB;
+    double* const prw = lbuf + (2 + buf) * 8 * kMaxB;
+    // (1) the block's columns, all rows
+    if (tx == kt) {
 #pragma unroll
-    for (int kc = 0; kc < 8; ++kc) {
-      const int k = 8 * kt + kc;
-      if (k >= bw) break;
-      const int buf = k & 1;
-      // (1) column k: its owners post it and their best key
-      uint64_t best = 0;
-      if (tx == kt) {
+      for (int c = 0; c < 8; ++c)
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const double v = T[kc][r];
-          colk[buf][8 * ty + r] = v;
-          const uint64_t key = ((usedm >> r) & 1u) ? 0ull : make_key(fabs(v), (uint32_t)(8 * ty + r));
-          best = key > best ? key : best;
-          T[kc][r] = 0.0;
-        }
+        for (int r = 0; r < 8; ++r) pan[c * kMaxB + 8 * ty + r] = T[c][r];
+    }
+    __syncthreads();
+    // (2) the block's steps on its own columns
+    if (wave == 0) {
+      double v0[8], v1[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        v0[c] = pan[c * kMaxB + lane];
+        v1[c] = pan[c * kMaxB + lane + 64];
       }
-      best = wave_max_key(best);
-      if ((tid & 63) == 0) wkeys[buf][wave] = best;
-      __syncthreads();
-      // (2) the winning row
-      const uint64_t kk = umax(umax(wkeys[buf][0], wkeys[buf][1]), umax(wkeys[buf][2], wkeys[buf][3]));
-      const int p = __builtin_amdgcn_readfirstlane((int)key_index(kk));
-      const bool zero = (kk >> kDropBits) == 0;
-      if (tid == 0) {
-        pivrow[k] = p;
-        slotof[p] = k;
-        if (zero && a.stats) set_info(a.stats, (int32_t)(a.k0 + k + 1));
-        if (key_nonfinite(kk) && a.stats) set_info(a.stats, -1);
-      }
-      if (ty == (p >> 3)) {
-        const double pv = colk[buf][p];
-        const double pinv = zero ? 0.0 : 1.0 / pv;
-        const int pr = p & 7;                 // uniform: indexes registers directly
+      int pk[8];
+      int ev = 0;                                // first info event of the block
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const uint64_t k0v = used0 ? 0ull : make_key(fabs(v0[kc]), (uint32_t)lane);
+        const uint64_t k1v = used1 ? 0ull : make_key(fabs(v1[kc]), (uint32_t)(lane + 64));
+        const uint64_t kk = wave_max_key(umax(k0v, k1v));
+        const int p = __builtin_amdgcn_readfirstlane((int)key_index(kk));
+        const bool zero = (kk >> kDropBits) == 0;
+        const int evk = zero ? (int)(a.k0 + 8 * kt + kc + 1) : (key_nonfinite(kk) ? -1 : 0);
+        ev = (ev == 0 && kc < nk) ? evk : ev;
+        pk[kc] = p;
+        const bool hi = p >= 64;
+        const int pl = p & 63;
         double rv[8];
 #pragma unroll
+        for (int c = 0; c < 8; ++c) rv[c] = readlane_d(hi ? v1[c] : v0[c], pl);
+        const double pinv = zero ? 0.0 : 1.0 / rv[kc];
+        // rows other than p: v -= g r, column kc becomes -g; row p becomes
+        // r / pivot with 1 / pivot in column kc (g = -1 / pivot)
+        const bool isp0 = lane == p, isp1 = lane + 64 == p;
+        const double g0 = (isp0 ? -1.0 : v0[kc]) * pinv;
+        const double g1 = (isp1 ? -1.0 : v1[kc]) * pinv;
+#pragma unroll
         for (int c = 0; c < 8; ++c) {
-          rv[c] = T[c][pr];
-          T[c][pr] = 0.0;
+          if (c == kc) {
+            v0[c] = -g0;
+            v1[c] = -g1;
+          } else {
+            v0[c] = fma(-g0, rv[c], isp0 ? 0.0 : v0[c]);
+            v1[c] = fma(-g1, rv[c], isp1 ? 0.0 : v1[c]);
+          }
         }
-        usedm |= 1u << pr;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) rowp[buf][8 * tx + c] = rv[c] * pinv;
-        if (tx == kt) {
-          rowp[buf][k] = pinv;
-          colk[buf][p] = -1.0;
-        }
+        used0 = used0 || isp0;
+        used1 = used1 || isp1;
       }
-      __syncthreads();
-      // (3) the rank-one step
-      double rp[8], f[8];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) rp[c] = rowp[buf][8 * tx + c];
+      for (int c = 0; c < 8; ++c) {
+        pan[c * kMaxB + lane] = v0[c];
+        pan[c * kMaxB + lane + 64] = v1[c];
+      }
+      int pme = pk[0];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) f[r] = colk[buf][8 * ty + r];
+      for (int kc = 1; kc < 8; ++kc) pme = (lane == kc) ? pk[kc] : pme;
+      if (lane < nk) {
+        pivrow[8 * kt + lane] = pme;
+        slotof[pme] = 8 * kt + lane;
+      }
+      if (lane == 0 && ev != 0 && a.stats) set_info(a.stats, ev);
+    }
+    __syncthreads();
+    // (3) the block's pivot rows as they were before it; pm marks this
+    // thread's rows among them
+    unsigned pm = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int kc = slotof[8 * ty + r] - 8 * kt;
+      if (kc >= 0 && kc < nk) {
+        pm |= 1u << r;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) prw[kc * kMaxB + 8 * tx + c] = T[c][r];
+      }
+    }
+    __syncthreads();
+    // (4) the update (surplus steps of a short last block add 0 x finite)
+    if (tx == kt) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) T[c][r] = pan[c * kMaxB + 8 * ty + r];
+    } else {
 #pragma unroll
       for (int r = 0; r < 8; ++r)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) T[c][r] = fma(-f[r], rp[c], T[c][r]);
+        for (int c = 0; c < 8; ++c) T[c][r] = ((pm >> r) & 1u) ? 0.0 : T[c][r];
+      // step kc + 1's operands are read while step kc's FMAs run
+      double f[2][8], rp[2][8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) f[0][r] = pan[8 * ty + r];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) rp[0][c] = prw[8 * tx + c];
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const int cb = kc & 1;
+        if (kc + 1 < 8) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) f[cb ^ 1][r] = pan[(kc + 1) * kMaxB + 8 * ty + r];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) rp[cb ^ 1][c] = prw[(kc + 1) * kMaxB + 8 * tx + c];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+          for (int c = 0; c < 8; ++c) T[c][r] = fma(f[cb][r], rp[cb][c], T[c][r]);
+      }
     }
   }
-  __syncthreads();
-  // entry (i, j) = W[q_i][p_j]
+  // entry (i, j) = W[q_i][p_j]: one wave's 32 rows at a time are put in
+  // place in LDS, then written as whole rows of W
+  int pc[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int i = 8 * ty + r;
-    if (i >= bw) continue;
-    const int wr = slotof[i];
+  for (int c = 0; c < 8; ++c) pc[c] = 8 * tx + c < bw ? pivrow[8 * tx + c] : 0;
+  for (int w = 0; w < kInvThreads / 64; ++w) {
+    __syncthreads();
+    if (32 * w >= bw) break;
+    if (wave == w) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int j = 8 * tx + c;
-      if (j < bw) W[(int64_t)wr * bw + pivrow[j]] = T[c][r];
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (8 * tx + c < bw) lbuf[(8 * ty + r - 32 * w) * kMaxB + pc[c]] = T[c][r];
     }
+    __syncthreads();
+    // this thread's column of rows 32 w + (tid >> 7) + 2 u: all reads first
+    constexpr int kU = 32 * kMaxB / kInvThreads;
+    const int col = tid % kMaxB, rr0 = tid / kMaxB;
+    double sv[kU];
+    int wr[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      sv[u] = lbuf[(rr0 + 2 * u) * kMaxB + col];
+      wr[u] = slotof[32 * w + rr0 + 2 * u];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (32 * w + rr0 + 2 * u < bw && col < bw) W[(int64_t)wr[u] * bw + col] = sv[u];
   }
 }
 
