@@ -395,9 +395,7 @@ struct Ctx {
     GeppArgs ga{A, lda, k0, bw, (int)m, sel(), PL(), mv(), mv() + 2 * kMaxB, mv() + 4 * kMaxB,
                 stats, p11(), panel_src, b};
     PhaseScope ps(0, st);
-    hipError_t e = launch_root_prep(ga, winners, sel(), srcmap(), st);
-    if (e != hipSuccess) return e;
-    e = launch_block_inverse(ga, winv(), st);
+    hipError_t e = launch_root(ga, winners, sel(), srcmap(), winv(), st);
     if (e != hipSuccess) return e;
     if (m > bw) {
       GemmArgs y{(int)(m - bw), bw, bw, panel_src ? panel_src : A + k0 * lda + k0,

@@ -313,13 +313,14 @@ hipError_t launch_plan_batched(const GeppArgs* list, int count, hipStream_t stre
 // pivoting of the panel transpose with the winners first gives
 // (R11^-1 R12)^T, which is the same matrix).  The root does it without a
 // cross-workgroup step: root_prep forms the moves of Pi_j and the source-row
-// map, block_inverse forms W = A11^-1 in one workgroup, and one gathered
-// GEMM writes the rows of Y = A21 W at their positions after the moves.
+// map while block_inverse forms W = A11^-1 (two workgroups of one launch,
+// independent of each other), and one gathered GEMM writes the rows of
+// Y = A21 W at their positions after the moves.
 
 // sel <- the winners (slot order); the moves of Pi_j as plan_kernel forms
 // them; srcmap[t - bw] = the panel row that lands at position t >= bw.
-__global__ __launch_bounds__(256) void root_prep_kernel(GeppArgs a, const int32_t* winners,
-                                                       int32_t* sel, int32_t* srcmap) {
+__device__ __forceinline__ void root_prep_body(const GeppArgs& a, const int32_t* winners,
+                                               int32_t* sel, int32_t* srcmap) {
   const int tid = threadIdx.x;
   if (tid < a.bw) sel[tid] = winners[tid];
   __syncthreads();              // plan_body reads a.sel == sel
@@ -333,11 +334,6 @@ __global__ __launch_bounds__(256) void root_prep_kernel(GeppArgs a, const int32_
   }
 }
 
-hipError_t launch_root_prep(const GeppArgs& a, const int32_t* winners, int32_t* sel,
-                            int32_t* srcmap, hipStream_t stream) {
-  hipLaunchKernelGGL(root_prep_kernel, dim3(1), dim3(256), 0, stream, a, winners, sel, srcmap);
-  return hipGetLastError();
-}
 
 // W = A11^-1 for the bw x bw block of the selected rows (slot order), by
 // Gauss-Jordan elimination with partial pivoting, in place, in registers.
@@ -367,7 +363,7 @@ hipError_t launch_root_prep(const GeppArgs& a, const int32_t* winners, int32_t* 
 // every row is used by then, so the winning key is 0 and the reciprocal 0.
 constexpr int kInvThreads = 256;
 
-__global__ __launch_bounds__(kInvThreads) void block_inverse_kernel(GeppArgs a, double* W) {
+__device__ __forceinline__ void block_inverse_body(const GeppArgs& a, double* W) {
   // lbuf: pan[2] (block columns: column c, row i at c kMaxB + i), then
   // prw[2] (old pivot rows: step kc, column j at kc kMaxB + j); at the end
   // the staging of 32 rows of W
@@ -556,8 +552,25 @@ __global__ __launch_bounds__(kInvThreads) void block_inverse_kernel(GeppArgs a, 
   }
 }
 
-hipError_t launch_block_inverse(const GeppArgs& a, double* W, hipStream_t stream) {
-  hipLaunchKernelGGL(block_inverse_kernel, dim3(1), dim3(kInvThreads), 0, stream, a, W);
+// The root's two parts in one launch: workgroup 0 inverts the winners' block
+// (reading the winners directly), workgroup 1 writes sel, the moves and the
+// source-row map.  Neither reads what the other writes.
+__global__ __launch_bounds__(kInvThreads) void root_kernel(GeppArgs a, const int32_t* winners,
+                                                          int32_t* sel, int32_t* srcmap,
+                                                          double* W) {
+  if (blockIdx.x == 0) {
+    GeppArgs b = a;
+    b.sel = winners;
+    block_inverse_body(b, W);
+  } else {
+    root_prep_body(a, winners, sel, srcmap);
+  }
+}
+
+hipError_t launch_root(const GeppArgs& a, const int32_t* winners, int32_t* sel, int32_t* srcmap,
+                       double* W, hipStream_t stream) {
+  hipLaunchKernelGGL(root_kernel, dim3(2), dim3(kInvThreads), 0, stream, a, winners, sel, srcmap,
+                     W);
   return hipGetLastError();
 }
 

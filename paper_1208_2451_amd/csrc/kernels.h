@@ -121,13 +121,12 @@ hipError_t launch_perm_top(const PermTopArgs& a, hipStream_t stream);
 hipError_t launch_perm_top_batched(const PermTopArgs* list, int count, int64_t max_k0,
                                    hipStream_t stream);
 hipError_t launch_gepp(const GeppArgs& a, hipStream_t stream);
-// CALU_PRRP root: sel <- winners, the moves of Pi_j (as launch_plan) and
-// srcmap[t - bw] = the panel row that lands at position t >= bw.
-hipError_t launch_root_prep(const GeppArgs& a, const int32_t* winners, int32_t* sel,
-                            int32_t* srcmap, hipStream_t stream);
-// W = A11^-1 (bw x bw, row-major, ld bw) of the selected rows' panel block
-// (a.sel, slot order), Gauss-Jordan with partial pivoting in one workgroup.
-hipError_t launch_block_inverse(const GeppArgs& a, double* W, hipStream_t stream);
+// CALU_PRRP root, one launch of two workgroups: sel <- winners, the moves of
+// Pi_j (as launch_plan) and srcmap[t - bw] = the panel row that lands at
+// position t >= bw; and W = A11^-1 (bw x bw, row-major, ld bw) of the
+// winners' panel block (slot order), Gauss-Jordan with partial pivoting.
+hipError_t launch_root(const GeppArgs& a, const int32_t* winners, int32_t* sel, int32_t* srcmap,
+                       double* W, hipStream_t stream);
 // U12 = L11^-1 Pi11^T A12 in place (p11 nullable: identity).
 hipError_t launch_trsm_u12(double* A, int64_t lda, int64_t k0, int bw, int64_t nr, double* amax1,
                            double* amax2, const int32_t* p11, hipStream_t stream);
