@@ -36,7 +36,9 @@ def _compare(A, b, tau, tree, tile_rows, tag=""):
 
 
 @pytest.mark.parametrize("tree", ["binary", "flat"])
-@pytest.mark.parametrize("n,b,tr", [(256, 16, 32), (300, 16, 40), (250, 16, 39), (200, 8, 24)])
+# b = 12 and 20: the root inverse ends on a block of 4 columns
+@pytest.mark.parametrize("n,b,tr", [(256, 16, 32), (300, 16, 40), (250, 16, 39), (200, 8, 24),
+                                    (230, 12, 30), (200, 20, 45)])
 def test_calu_random(tree, n, b, tr):
     A, _ = inputs.randn_system(n, n + b + tr)
     _compare(A, b, 2.0, tree, tr, tag="randn")
