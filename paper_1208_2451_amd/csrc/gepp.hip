@@ -352,12 +352,12 @@ __device__ __forceinline__ void root_prep_body(const GeppArgs& a, const int32_t*
 //      with no barrier and no branch (lane l holds rows l and l + 64): a row
 //      i != p takes v -= g_i r with g_i = v_ik / pivot and r the pivot row, so
 //      the reciprocal feeds the FMAs directly; the block's columns then hold
-//      T, the columns p_k of the block's accumulated transform;
+//      X, the columns p_k of the block's accumulated transform;
 //  (3) the holders of the block's pivot rows post those rows as they were
 //      before the block;
 //  (4) every other column takes S[i][j] = [i not a pivot row of the block]
-//      S[i][j] + sum_k T[i][k] S_old[p_k][j], a rank-8 update, and the
-//      block's columns take T.
+//      S[i][j] + sum_k X[i][k] S_old[p_k][j], a rank-8 update, and the
+//      block's columns take X.
 // Three barriers per 8 columns; the LDS buffers alternate between blocks.
 // A last block of fewer than 8 columns runs its surplus steps as no-ops:
 // every row is used by then, so the winning key is 0 and the reciprocal 0.
